@@ -1,0 +1,274 @@
+"""Seeded synthetic workloads for the CDBM hot path.
+
+This module only *describes* runs: grid shapes, spacings, time steps,
+relaxation times, the adjustable discrete-velocity parameters of Eqs. (2)-(3),
+boundary conditions and the initial macroscopic fields (rho, u_x, u_y, T).
+It holds none of the method's arithmetic (no moments, no equilibrium, no
+fluxes), so both the HIP path and the CPU oracle can consume it without
+sharing any of the computation that the parity tests compare.
+
+Velocity-set parameters are the ones printed in Sec. 3 for each benchmark:
+Sod tube (Sec. 3.1), Lax tube (Sec. 3.2), Ma = 15 shock (Sec. 3.3), sound wave
+(Sec. 3.4) and Taylor-Green vortex (Sec. 3.5).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Tuple
+
+import numpy as np
+
+PERIODIC = 0
+ZERO_GRADIENT = 1
+
+# (v_a, v_b, v_c, v_d), (eta_a, eta_b, eta_c, eta_d) as printed in Sec. 3.
+VELOCITY_SETS = {
+    "sod": ((2.5, 2.5, 1.2, 1.1), (0.0, 0.0, 0.0, 1.2)),        # Sec. 3.1
+    "lax": ((4.4, 4.4, 3.0, 1.8), (0.0, 0.0, 5.0, 0.0)),        # Sec. 3.2
+    "shock": ((21.8, 21.8, 17.8, 9.8), (18.8, 0.0, 0.0, 0.0)),  # Sec. 3.3
+    "sound": ((1.4, 1.1, 1.1, 1.0), (3.0, 0.0, 0.0, 0.0)),      # Sec. 3.4
+    "tg": ((0.2, 0.2, 2.0, 2.0), (0.0, 5.0, 0.0, 2.6)),         # Sec. 3.5
+}
+
+
+@dataclasses.dataclass
+class Run:
+    """One run of the method: grid, parameters and initial fields.
+
+    Fields are float64 numpy arrays of shape (ny, nx), x fastest; cell j sits
+    at x = (j + 1/2) dx (cell-centred grid).
+    """
+
+    name: str
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    dt: float
+    tau: float
+    gamma: float
+    v: Tuple[float, float, float, float]
+    eta: Tuple[float, float, float, float]
+    bc_x: int
+    bc_y: int
+    steps: int
+    rho: np.ndarray
+    ux: np.ndarray
+    uy: np.ndarray
+    T: np.ndarray
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny
+
+    def with_fields(self, rho, ux, uy, T, **kw) -> "Run":
+        return dataclasses.replace(self, rho=rho, ux=ux, uy=uy, T=T, **kw)
+
+
+def cell_centres(n: int, d: float, origin: float = 0.0) -> np.ndarray:
+    return origin + (np.arange(n, dtype=np.float64) + 0.5) * d
+
+
+def _two_state(nx, ny, x, x_split, left, right):
+    """Piecewise-constant (rho, u_x, u_y, T) with the left state for x < x_split."""
+    mask = np.broadcast_to((x < x_split)[None, :], (ny, nx))
+    out = []
+    for l, r in zip(left, right):
+        out.append(np.where(mask, float(l), float(r)).astype(np.float64))
+    return out
+
+
+def sod_tube(nx: int = 500, dx: float = 2e-3, dt: float = 2e-5, tau: float = 2e-5,
+             gamma: float = 1.4, steps: int = 5000, vset: str = "sod") -> Run:
+    """Sod-type Riemann tube on an nx x 1 grid, diaphragm at the middle.
+
+    States are the Sec. 3.1 ones, (rho, u_x, u_y, T) = (1, 0, 0, 1) | (0.125, 0, 0, 0.8),
+    i.e. p = rho T = 1 | 0.1.  Zero-gradient ends in x; periodic in y (one row).
+    """
+    x = cell_centres(nx, dx)
+    rho, ux, uy, T = _two_state(nx, 1, x, 0.5 * nx * dx, (1.0, 0.0, 0.0, 1.0),
+                                (0.125, 0.0, 0.0, 0.8))
+    v, eta = VELOCITY_SETS[vset]
+    return Run("sod", nx, 1, dx, dx, dt, tau, gamma, v, eta, ZERO_GRADIENT, PERIODIC,
+               steps, rho, ux, uy, T)
+
+
+def lax_tube(nx: int = 1000, dx: float = 2e-3, dt: float = 2e-5, tau: float = 1e-4,
+             gamma: float = 1.4, steps: int = 10000) -> Run:
+    """The Sec. 3.2 Lax tube: L = (0.445, 0.698, 0, 7.928) on [0,1), R = (0.5, 0, 0, 1.142)."""
+    x = cell_centres(nx, dx)
+    rho, ux, uy, T = _two_state(nx, 1, x, 1.0, (0.445, 0.698, 0.0, 7.928),
+                                (0.5, 0.0, 0.0, 1.142))
+    v, eta = VELOCITY_SETS["lax"]
+    return Run("lax", nx, 1, dx, dx, dt, tau, gamma, v, eta, ZERO_GRADIENT, PERIODIC,
+               steps, rho, ux, uy, T)
+
+
+def taylor_green_paper(n: int = 100, t_end: float = 0.1, dt: float = 2e-5) -> Run:
+    """The Sec. 3.5 Taylor-Green vortex on [0, 2L]^2 at t = 0 (Eqs. (22)-(24)).
+
+    u0 = 0.01, p0 = 1, L = 0.05, rho0 = 1 (so T = p), gamma = 1.4, tau = 5e-4.
+    """
+    u0, p0, L = 0.01, 1.0, 0.05
+    d = 2 * L / n
+    x = cell_centres(n, d)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    ux = -u0 * np.cos(np.pi * X / L) * np.sin(np.pi * Y / L)
+    uy = u0 * np.sin(np.pi * X / L) * np.cos(np.pi * Y / L)
+    p = p0 - p0 * u0 ** 2 / 4 * (np.cos(2 * np.pi * X / L) + np.cos(2 * np.pi * Y / L))
+    rho = np.ones_like(p)
+    v, eta = VELOCITY_SETS["tg"]
+    steps = int(round(t_end / dt))
+    return Run("taylor_green_paper", n, n, d, d, dt, 5e-4, 1.4, v, eta, PERIODIC, PERIODIC,
+               steps, rho, ux, uy, p / rho)
+
+
+def taylor_green_2pi(n: int = 512, U0: float = 0.1, tau: float = 1e-4, dt: float = 1e-4,
+                     steps: int = 10000, gamma: float = 1.4) -> Run:
+    """Taylor-Green vortex on [0, 2 pi)^2: u = U0 sin x cos y, v = -U0 cos x sin y.
+
+    rho = 1 and the incompressible pressure p = 1 + (U0^2/4)(cos 2x + cos 2y)
+    (the sign that balances (u.grad)u for this velocity field), T = p / rho.
+    Velocity set: the Sec. 3.5 one.
+    """
+    d = 2 * np.pi / n
+    x = cell_centres(n, d)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    ux = U0 * np.sin(X) * np.cos(Y)
+    uy = -U0 * np.cos(X) * np.sin(Y)
+    p = 1.0 + U0 ** 2 / 4 * (np.cos(2 * X) + np.cos(2 * Y))
+    rho = np.ones_like(p)
+    v, eta = VELOCITY_SETS["tg"]
+    return Run("taylor_green_2pi", n, n, d, d, dt, tau, gamma, v, eta, PERIODIC, PERIODIC,
+               steps, rho, ux, uy, p / rho)
+
+
+HEADLINE_GAMMAS = (1.2, 1.4, 5.0 / 3.0)
+
+
+def lax_acoustic_2d(n: int = 4096, seed: int = 0, steps: int = 2000, ny: int | None = None,
+                    length: float = 2.0, dt: float = 2e-5, tau: float = 1e-4,
+                    gamma: float | None = None) -> Run:
+    """Lax tube extruded in y with an oblique density wave on top (the headline workload).
+
+    Domain [0, length) x [0, length * ny / n) with dx = dy = length / n.  Lax states
+    of Sec. 3.2 with the diaphragm at x = length / 2; the density is multiplied by
+    1 + 1e-3 cos(2 pi (2 x / length + 3 y / length) + phi).  phi ~ U[0, 2 pi) and,
+    unless given, gamma ~ U{1.2, 1.4, 5/3}, both from numpy's default_rng(seed).
+    Zero-gradient in x, periodic in y; Lax velocity set.
+    """
+    ny = n if ny is None else ny
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(0.0, 2 * np.pi)
+    g_pick = HEADLINE_GAMMAS[int(rng.integers(0, len(HEADLINE_GAMMAS)))]
+    if gamma is None:
+        gamma = g_pick
+    d = length / n
+    x = cell_centres(n, d)
+    y = cell_centres(ny, d)
+    rho, ux, uy, T = _two_state(n, ny, x, 0.5 * length, (0.445, 0.698, 0.0, 7.928),
+                                (0.5, 0.0, 0.0, 1.142))
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    rho = rho * (1.0 + 1e-3 * np.cos(2 * np.pi * (2 * X / length + 3 * Y / length) + phi))
+    v, eta = VELOCITY_SETS["lax"]
+    return Run(f"lax_acoustic_{n}x{ny}_seed{seed}", n, ny, d, d, dt, tau, gamma, v, eta,
+               ZERO_GRADIENT, PERIODIC, steps, rho, ux, uy, T)
+
+
+def fourier_field(rng: np.random.Generator, nx: int, ny: int, modes: int = 5) -> np.ndarray:
+    """Periodic sum of `modes` plane waves with wave numbers in {1..4}^2 (domain [0,1)^2),
+    random amplitudes and phases, normalised so that max |s| = 1."""
+    x = cell_centres(nx, 1.0 / nx)
+    y = cell_centres(ny, 1.0 / ny)
+    X, Y = np.meshgrid(x, y, indexing="xy")
+    s = np.zeros((ny, nx))
+    for _ in range(modes):
+        kx, ky = rng.integers(1, 5, size=2)
+        amp = rng.uniform(0.2, 1.0)
+        ph = rng.uniform(0.0, 2 * np.pi)
+        s += amp * np.cos(2 * np.pi * (kx * X + ky * Y) + ph)
+    return s / np.abs(s).max()
+
+
+def smooth_random_fields(rng: np.random.Generator, nx: int, ny: int, umax: float = 0.29):
+    """rho, T in [0.5, 2] as 1.25 + 0.75 s and a velocity with max |u| = umax."""
+    rho = 1.25 + 0.75 * fourier_field(rng, nx, ny)
+    T = 1.25 + 0.75 * fourier_field(rng, nx, ny)
+    ux = fourier_field(rng, nx, ny)
+    uy = fourier_field(rng, nx, ny)
+    mag = np.sqrt(ux ** 2 + uy ** 2).max()
+    return rho, ux * umax / mag, uy * umax / mag, T
+
+
+def random_periodic(nx: int, ny: int, seed: int, dt: float = 1e-5, tau: float = 1e-4,
+                    gamma: float = 1.4, vset: str = "sound", steps: int = 1,
+                    umax: float = 0.29) -> Run:
+    """Smooth random fields on a periodic [0,1)^2 grid (dx = 1/nx, dy = 1/ny)."""
+    rng = np.random.default_rng(seed)
+    rho, ux, uy, T = smooth_random_fields(rng, nx, ny, umax)
+    v, eta = VELOCITY_SETS[vset]
+    return Run(f"random_{nx}x{ny}_seed{seed}", nx, ny, 1.0 / nx, 1.0 / ny, dt, tau, gamma,
+               v, eta, PERIODIC, PERIODIC, steps, rho, ux, uy, T)
+
+
+BATCH_SIZES = tuple(range(128, 1025, 64))
+
+
+def batched_ensemble(ngrids: int = 96, seed: int = 0, dt: float = 1e-5, steps: int = 1000,
+                     sizes: Tuple[int, ...] = BATCH_SIZES, vset: str = "sound") -> List[Run]:
+    """Independent periodic [0,1)^2 grids of uneven size, each with its own gamma and tau.
+
+    N ~ U{sizes}, gamma ~ U[1.1, 1.67], tau = 10^U[-5, -3]; fields from smooth_random_fields.
+    """
+    rng = np.random.default_rng(seed)
+    runs = []
+    for g in range(ngrids):
+        n = int(sizes[int(rng.integers(0, len(sizes)))])
+        gamma = float(rng.uniform(1.1, 1.67))
+        tau = float(10.0 ** rng.uniform(-5.0, -3.0))
+        rho, ux, uy, T = smooth_random_fields(rng, n, n)
+        v, eta = VELOCITY_SETS[vset]
+        runs.append(Run(f"batch{g}_{n}", n, n, 1.0 / n, 1.0 / n, dt, tau, gamma, v, eta,
+                        PERIODIC, PERIODIC, steps, rho, ux, uy, T))
+    return runs
+
+
+def adjoint_problem(n: int = 256, seed: int = 0, steps: int = 2000, dt: float = 2e-5,
+                    tau: float = 1e-4, gamma: float = 1.4, perturb: float = 0.01):
+    """Initial fields and a perturbed target run for the gradient workload.
+
+    Returns (run, target_run): the target starts from fields perturbed by `perturb`
+    times an independent smooth field (seed + 1) and uses tau * 1.1.
+    """
+    base = random_periodic(n, n, seed, dt=dt, tau=tau, gamma=gamma, steps=steps)
+    rng = np.random.default_rng(seed + 1)
+    pr = fourier_field(rng, n, n)
+    pu = fourier_field(rng, n, n)
+    pv = fourier_field(rng, n, n)
+    pt = fourier_field(rng, n, n)
+    tgt = base.with_fields(base.rho * (1 + perturb * pr), base.ux + perturb * 0.29 * pu,
+                           base.uy + perturb * 0.29 * pv, base.T * (1 + perturb * pt),
+                           tau=tau * 1.1, name=base.name + "_target")
+    return base, tgt
+
+
+def uniform(nx: int, ny: int, rho=1.0, ux=0.0, uy=0.0, T=1.0, vset="sound", dt=1e-5,
+            tau=1e-4, gamma=1.4, dx=None) -> Run:
+    dx = 1.0 / nx if dx is None else dx
+    v, eta = VELOCITY_SETS[vset]
+    full = lambda c: np.full((ny, nx), float(c))
+    return Run("uniform", nx, ny, dx, dx, dt, tau, gamma, v, eta, PERIODIC, PERIODIC, 1,
+               full(rho), full(ux), full(uy), full(T))
+
+
+def headline(seed: int = 0, steps: int = 2000) -> Run:
+    return lax_acoustic_2d(4096, seed=seed, steps=steps)
+
+
+def small_headline(n: int = 512, seed: int = 0, steps: int = 2000) -> Run:
+    """The headline setup at a smaller square grid (same physical domain)."""
+    return lax_acoustic_2d(n, seed=seed, steps=steps)
+
+
+__all__ = [n for n in dir() if not n.startswith("_")]
