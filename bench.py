@@ -1,0 +1,175 @@
+"""Benchmark of the CDBM hot path on one MI355X.
+
+One step = one full time step (both Runge-Kutta stages) of the headline
+workload: the Lax tube extruded in y with an oblique density wave on a
+4096 x 4096 grid, f stored in FP32 with FP64 moments and equilibrium
+(the mixed form).  The metric is cell-velocity updates per second
+(16 * cells * steps / time); the fused step kernel is also priced against
+the HBM roofline (8 bytes per update in the mixed form: f^n read once,
+f^{n+1} written once).  Beside it: the FP64 form on the same workload, the
+adjoint/forward time ratio on the 256 x 256 gradient workload, and the CPU
+oracle timed on a bounded sample of the headline workload.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_fused_mixed_4096_traffic.json")
+KERNEL_SOURCES = ["cell.hpp", "step_fused.hpp", "kernels_step.hip"]
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2502_16818_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--n", type=int, default=4096, help="grid side of the headline workload")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1024, help="grid side of the oracle sample")
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    return ap.parse_args()
+
+
+def time_steps(solver, f_a, f_b, steps, warmup):
+    """Average time of one step over `steps` steps, measured with HIP events
+    on the stream the library launches on (torch's current stream)."""
+    import torch
+    if warmup > 0:
+        solver.step(f_a, f_b, nsteps=warmup)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    e0.record(st)
+    solver.step(f_a, f_b, nsteps=steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    return e0.elapsed_time(e1) / 1e3 / steps, wall
+
+
+def cpu_baseline(run_full, side, steps):
+    """The oracle, as it stands, on a side x side sample of the headline setup."""
+    import torch
+    import workloads as W
+    from oracle import cdbm as C
+    run = W.headline_sample(side, seed=run_full_seed(run_full))
+    p = C.Params.from_run(run)
+    f = C.initial_distribution(run.rho, run.ux, run.uy, run.T, p)
+    f = C.step(f, p)   # warm-up
+    t0 = time.perf_counter()
+    f = C.run(f, p, steps)
+    el = time.perf_counter() - t0
+    ups = 16 * run.cells * steps / el
+    return {"value": ups, "unit": "cell-velocity updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{side}x{side} cells of the headline setup (same dx, dt, tau, gamma, "
+                      f"velocity set), {steps} FP64 steps after one warm-up step, "
+                      f"{el:.1f} s"}
+
+
+def run_full_seed(run):
+    return int(run.name.rsplit("seed", 1)[-1])
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU decomposition is described, not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads as W
+    from paper_2502_16818_amd import FP64, MIXED, Solver
+
+    run = W.headline(seed=args.seed, n=args.n)
+    out = {}
+
+    # mixed form: the headline number
+    s = Solver.from_run(run, MIXED)
+    fa = s.init(run.rho, run.ux, run.uy, run.T)
+    fb = s.empty_f()
+    t_mixed, wall = time_steps(s, fa, fb, args.steps, args.warmup)
+    ups = 16 * run.cells / t_mixed
+    alg_bytes = 2 * 4 * 16 * run.cells           # per launch of the fused step
+    achieved = alg_bytes / t_mixed / 1e9
+    digest = kernel_digest()
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tf = json.load(open(TRAFFIC_FILE))
+        if tf.get("kernel_digest") == digest and tf.get("workload") == run.name:
+            traffic = tf.get("bytes_per_launch")
+    out.update({
+        "metric": "cell-velocity updates/s (4096^2, mixed FP32/FP64)",
+        "value": ups,
+        "unit": "cell-velocity updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_mixed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage+advection, f64 moments/equilibrium",
+        "data": "synthetic (seeded Lax tube x oblique acoustic wave)",
+        "config": {"workload": run.name, "nx": run.nx, "ny": run.ny, "dx": run.dx,
+                   "dt": run.dt, "tau": run.tau, "gamma": run.gamma, "v": list(run.v),
+                   "eta": list(run.eta), "bc": "zero-gradient x, periodic y",
+                   "precision": "mixed"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_step_fused<float>", "alg_bytes_per_launch": alg_bytes,
+                     "kernel_digest": digest},
+        "wall_s_timed": wall,
+    })
+    del fa, fb
+    s.close()
+
+    if not args.no_fp64:
+        s = Solver.from_run(run, FP64)
+        fa = s.init(run.rho, run.ux, run.uy, run.T)
+        fb = s.empty_f()
+        nst = max(args.steps // 2, 10)
+        t64, _ = time_steps(s, fa, fb, nst, args.warmup)
+        ach64 = 2 * 8 * 16 * run.cells / t64 / 1e9
+        out["fp64"] = {"value": 16 * run.cells / t64, "ms_per_step": t64 * 1e3, "steps": nst,
+                       "roofline_frac": ach64 / HBM_PEAK_GBS, "achieved_GBs": ach64}
+        out["speedup_mixed_over_fp64"] = t64 / t_mixed
+        del fa, fb
+        s.close()
+
+    if not args.no_adjoint:
+        try:
+            from paper_2502_16818_amd.rollout import adjoint_forward_ratio
+            out["adjoint"] = adjoint_forward_ratio()
+        except ImportError:
+            out["adjoint"] = None
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(run, args.cpu_sample, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * cdbm.h - C ABI of the MI355X (gfx950) implementation of the central-moment
+ * discrete Boltzmann method (CDBM) for compressible flows with a variable
+ * specific-heat ratio (C. Lin, X. Su, L. Fei, K. H. Luo, arXiv:2502.16818).
+ *
+ * One time step, per cell and per discrete velocity i = 1..16:
+ *   - macroscopic rho, u, T from the first three kinetic moments (Sec. 2,
+ *     the statement after Eq. (7));
+ *   - the equilibrium f_i^eq that reproduces the seven central moments of
+ *     the Maxwellian, Eqs. (4)-(7) (computed as the raw-moment vector of the
+ *     Maxwellian contracted with one shared inverse moment matrix; the
+ *     central-to-raw shift is exact, so the result equals Eq. (7));
+ *   - BGK relaxation -(f_i - f_i^eq)/tau of Eq. (1);
+ *   - the NND flux-split upwind derivative with minmod, Eqs. (12)-(20);
+ *   - a two-stage second-order Runge-Kutta step (Heun form).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Distributions are structure-of-arrays f[i][y][x], x fastest, i = 0..15
+ *   for the paper's i = 1..16, ordered as: v_a(1,0), v_a(0,1), v_a(-1,0),
+ *   v_a(0,-1); v_b(1,1), v_b(-1,1), v_b(-1,-1), v_b(1,-1); then groups c
+ *   (axis) and d (diagonal) in the same order (Eq. (2)); eta_i per group
+ *   (Eq. (3)).  Element type: double for CDBM_FP64, float for CDBM_MIXED.
+ * - Macroscopic fields are double arrays [y][x].
+ * - Every pointer argument named as device memory must point to memory of
+ *   the GPU that is current when the call is made.  The caller owns all
+ *   device buffers; the library owns only its handle, a few constant and
+ *   scratch buffers it allocates at creation, and captured graphs.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Calls are asynchronous on that stream unless documented otherwise.
+ * - Every call returns 0 (CDBM_OK) or a negative error code; it never
+ *   throws or aborts.  cdbm_last_error() returns a thread-local message
+ *   describing the last failure of the calling thread.
+ * - Calls on one handle must not run concurrently from several threads.
+ */
+#ifndef CDBM_H
+#define CDBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CDBM_OK = 0,
+    CDBM_EINVAL = -1,     /* an argument is out of range or inconsistent          */
+    CDBM_ESINGULAR = -2,  /* the moment matrix of the velocity set is singular or
+                             too ill-conditioned (block condition number > 1e10) */
+    CDBM_ENONPHYS = -3,   /* rho <= 0, T <= 0 or a non-finite value in the fields */
+    CDBM_EHIP = -4,       /* a HIP runtime call failed                            */
+    CDBM_ENOMEM = -5      /* a library allocation failed                          */
+};
+
+enum { CDBM_PERIODIC = 0, CDBM_ZERO_GRADIENT = 1 };
+enum { CDBM_FP64 = 0, CDBM_MIXED = 1 };
+
+/* Run parameters (Secs. 2 and 3).
+ *   nx, ny      grid cells (ny = 1 for a tube); 1 <= nx, ny <= 65536 and
+ *               nx*ny <= 2^28.
+ *   dx, dy      cell sizes (> 0).  dt: time step (> 0).  tau: relaxation
+ *               time of Eq. (1) (> 0); dt/tau <= 2 is required (the stable
+ *               interval of the two-stage scheme for pure relaxation).
+ *   gamma       specific-heat ratio, 1 < gamma <= 2; the extra degrees of
+ *               freedom are I = 2/(gamma-1) - 2 (gamma = (D+I+2)/(D+I), D = 2).
+ *   v[4]        (v_a, v_b, v_c, v_d) of Eq. (2), each > 0.  Diagonal groups
+ *               have components +-v (speed sqrt(2) v).
+ *   eta[4]      (eta_a, eta_b, eta_c, eta_d) of Eq. (3), each >= 0.
+ *   bc_x, bc_y  CDBM_PERIODIC or CDBM_ZERO_GRADIENT (two ghost layers per
+ *               side copied from the edge cell before each stage).
+ *   precision   CDBM_FP64: f stored and advected in double.  CDBM_MIXED: f
+ *               stored and advected in float; moments, equilibrium and the
+ *               relaxation difference f - f^eq in double. */
+typedef struct cdbm_params {
+    int32_t nx, ny;
+    double dx, dy, dt, tau;
+    double gamma;
+    double v[4];
+    double eta[4];
+    int32_t bc_x, bc_y;
+    int32_t precision;
+} cdbm_params;
+
+typedef struct cdbm_handle cdbm_handle;
+typedef struct cdbm_batch cdbm_batch;
+
+/* Thread-local description of the calling thread's last error ("" if none). */
+const char* cdbm_last_error(void);
+
+/* Validate `p`, build the 16x16 moment matrix of the velocity set at u = 0
+ * (rows of Eq. (6)), split it into its four parity blocks and invert them in
+ * extended precision on the host; allocate the handle's scratch (one f-sized
+ * ping-pong buffer and reduction partials) on the current device.
+ * Synchronous.  Errors: EINVAL, ESINGULAR, ENOMEM, EHIP. */
+int cdbm_create(const cdbm_params* p, cdbm_handle** out);
+
+/* Release everything the handle owns.  NULL is accepted.  Synchronizes the
+ * device before freeing. */
+int cdbm_destroy(cdbm_handle* h);
+
+/* Copy of the parameters the handle was created with. */
+int cdbm_get_params(const cdbm_handle* h, cdbm_params* out);
+
+/* f = f^eq(rho, u, T) in every cell (the initial condition used in Sec. 3).
+ * rho, ux, uy, T: device double [ny][nx]; f_out: device [16][ny][nx].
+ * Checks the fields on the device first and returns ENONPHYS (f_out
+ * untouched) if any rho or T is <= 0 or any value is not finite; this check
+ * synchronizes `stream`. */
+int cdbm_init(cdbm_handle* h, const double* rho, const double* ux, const double* uy,
+              const double* T, void* f_out, void* stream);
+
+/* Advance `nsteps` >= 0 time steps of Eq. (1) (NND in space, Eqs. (12)-(20);
+ * Heun RK2 in time) from f_in to f_out (device [16][ny][nx]).  f_in is not
+ * modified; f_out must not overlap f_in.  The library ping-pongs between
+ * f_out and its own scratch buffer so that the result lands in f_out.
+ * nsteps = 0 copies f_in to f_out. */
+int cdbm_step(cdbm_handle* h, const void* f_in, void* f_out, int32_t nsteps, void* stream);
+
+/* Macroscopic fields of f (Sec. 2, statement after Eq. (7)): rho = sum f_i,
+ * rho u = sum f_i v_i, rho (D+I) T = sum f_i (|v_i - u|^2 + eta_i^2).
+ * Outputs: device double [ny][nx] each. */
+int cdbm_moments(cdbm_handle* h, const void* f, double* rho, double* ux, double* uy,
+                 double* T, void* stream);
+
+/* Thermodynamic nonequilibrium measures, Eqs. (8)-(11):
+ * out12[k][y][x] (device double, 12 planes) = sum_i (f_i - f_i^eq) Psi_{k+5}(v_i - u)
+ * in the row order of Eq. (6): Delta*_2 (xx, xy, yy), Delta*_{3,1} (x, y),
+ * Delta*_3 (xxx, xxy, xyy, yyy), Delta*_{4,2} (xx, xy, yy). */
+int cdbm_tne(cdbm_handle* h, const void* f, double* out12, void* stream);
+
+/* Grid totals of mass, x- and y-momentum and energy (sum over cells of
+ * rho, rho u_x, rho u_y and sum_i f_i (|v_i|^2 + eta_i^2)), accumulated in
+ * double.  out4: device double[4], overwritten. */
+int cdbm_conserved_totals(cdbm_handle* h, const void* f, double* out4, void* stream);
+
+/* Reverse-mode product of one time step F (the map of cdbm_step with
+ * nsteps = 1): lam_n = (dF/df)^T(f_n) lam_np1 and *dL_dtau += (dF/dtau)^T lam_np1.
+ * f_n, lam_np1, lam_n: device [16][ny][nx] in the handle's precision;
+ * lam_n must not overlap f_n or lam_np1.  dL_dtau: device double[1],
+ * accumulated (never overwritten).  minmod passes the derivative to its first
+ * argument on a tie |X| = |Y| and none when its value is 0 (the branch order
+ * of Eq. (16)).  Uses the handle's scratch buffer, so calls on one handle
+ * must be ordered on one stream. */
+int cdbm_step_adjoint(cdbm_handle* h, const void* f_n, const void* lam_np1, void* lam_n,
+                      double* dL_dtau, void* stream);
+
+/* Reverse-mode product of cdbm_init: g_q = (d f^eq(q) / d q)^T lam_f0 for
+ * q = (rho, u_x, u_y, T) taken from the given fields (device double [ny][nx]).
+ * lam_f0: device [16][ny][nx] in the handle's precision.  Outputs overwritten. */
+int cdbm_init_adjoint(cdbm_handle* h, const double* rho, const double* ux, const double* uy,
+                      const double* T, const void* lam_f0, double* g_rho, double* g_ux,
+                      double* g_uy, double* g_T, void* stream);
+
+/* Reverse-mode product of cdbm_moments: lam_f = (d(rho, u, T)/df)^T g.
+ * g_*: device double [ny][nx]; lam_f: device [16][ny][nx], overwritten. */
+int cdbm_moments_adjoint(cdbm_handle* h, const void* f, const double* g_rho,
+                         const double* g_ux, const double* g_uy, const double* g_T,
+                         void* lam_f, void* stream);
+
+/* Batched ensemble of independent grids advanced by one launch per step.
+ * per_grid[k]: parameters of grid k; v, eta and precision must be the same
+ * for all grids (one shared inverse moment matrix), everything else may
+ * differ.  f_offsets[k]: element offset of grid k's [16][ny][nx] block inside
+ * the caller's batch buffers (blocks must not overlap).  Both arrays are
+ * host memory, copied.  Synchronous.  Errors as cdbm_create. */
+int cdbm_batch_create(const cdbm_params* per_grid, int32_t ngrids, const int64_t* f_offsets,
+                      cdbm_batch** out);
+int cdbm_batch_destroy(cdbm_batch* b);
+
+/* f = f^eq of the fields of every grid.  The four fields are concatenated
+ * grid after grid (grid k's cells start at f_offsets[k] / 16).
+ * Same checks and synchronization as cdbm_init. */
+int cdbm_batch_init(cdbm_batch* b, const double* rho, const double* ux, const double* uy,
+                    const double* T, void* f_out, void* stream);
+
+/* Advance every grid of the batch by nsteps (each with its own dt, tau,
+ * gamma, dx, dy, sizes and boundary conditions).  Same buffer contract as
+ * cdbm_step; the per-step launch is captured once into a HIP graph and
+ * replayed. */
+int cdbm_batch_step(cdbm_batch* b, const void* f_in, void* f_out, int32_t nsteps, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDBM_H */

@@ -1,0 +1,275 @@
+"""Thin Python binding of libcdbm.so (include/cdbm.h) over torch device tensors.
+
+Only argument marshalling happens here: every step of the method runs in the
+HIP kernels behind the C ABI.  torch provides device memory and the current
+stream.  If the library has not been built, or no GPU is present, the calls
+raise instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcdbm.so")
+
+OK, EINVAL, ESINGULAR, ENONPHYS, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5
+PERIODIC, ZERO_GRADIENT = 0, 1
+FP64, MIXED = 0, 1
+
+EXPORTS = (
+    "cdbm_last_error", "cdbm_create", "cdbm_destroy", "cdbm_get_params", "cdbm_init",
+    "cdbm_step", "cdbm_moments", "cdbm_tne", "cdbm_conserved_totals", "cdbm_step_adjoint",
+    "cdbm_init_adjoint", "cdbm_moments_adjoint", "cdbm_batch_create", "cdbm_batch_destroy",
+    "cdbm_batch_init", "cdbm_batch_step",
+)
+
+
+class CdbmError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed with code {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
+        ("tau", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("v", ctypes.c_double * 4), ("eta", ctypes.c_double * 4),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("precision", ctypes.c_int32),
+    ]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+
+
+def load() -> ctypes.CDLL:
+    """Load libcdbm.so and declare the signatures of include/cdbm.h."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2502_16818_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(Params)
+    sig = {
+        "cdbm_last_error": ([], ctypes.c_char_p),
+        "cdbm_create": ([P, ctypes.POINTER(_vp)], _i32),
+        "cdbm_destroy": ([_vp], _i32),
+        "cdbm_get_params": ([_vp, P], _i32),
+        "cdbm_init": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
+        "cdbm_step": ([_vp, _vp, _vp, _i32, _vp], _i32),
+        "cdbm_moments": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
+        "cdbm_tne": ([_vp, _vp, _vp, _vp], _i32),
+        "cdbm_conserved_totals": ([_vp, _vp, _vp, _vp], _i32),
+        "cdbm_step_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp], _i32),
+        "cdbm_init_adjoint": ([_vp] * 11, _i32),
+        "cdbm_moments_adjoint": ([_vp] * 8, _i32),
+        "cdbm_batch_create": ([P, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_vp)], _i32),
+        "cdbm_batch_destroy": ([_vp], _i32),
+        "cdbm_batch_init": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
+        "cdbm_batch_step": ([_vp, _vp, _vp, _i32, _vp], _i32),
+    }
+    for name, (args, res) in sig.items():
+        if not hasattr(lib, name):
+            continue
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != OK:
+        raise CdbmError(rc, where, load().cdbm_last_error().decode())
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("CDBM buffers must be device tensors")
+    if not t.is_contiguous():
+        raise ValueError("CDBM buffers must be contiguous")
+    return t.data_ptr()
+
+
+def gamma_to_extra_dof(gamma: float) -> float:
+    return 2.0 / (gamma - 1.0) - 2.0
+
+
+def make_params(nx, ny, dx, dy, dt, tau, gamma, v, eta, bc_x=PERIODIC, bc_y=PERIODIC,
+                precision=FP64) -> Params:
+    p = Params()
+    p.nx, p.ny = int(nx), int(ny)
+    p.dx, p.dy, p.dt, p.tau, p.gamma = float(dx), float(dy), float(dt), float(tau), float(gamma)
+    for k in range(4):
+        p.v[k] = float(v[k])
+        p.eta[k] = float(eta[k])
+    p.bc_x, p.bc_y, p.precision = int(bc_x), int(bc_y), int(precision)
+    return p
+
+
+class Solver:
+    """One grid of the method behind a cdbm_handle."""
+
+    def __init__(self, params: Params):
+        lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the CDBM library needs a GPU")
+        h = _vp()
+        _check(lib.cdbm_create(ctypes.byref(params), ctypes.byref(h)), "cdbm_create")
+        self._h = h
+        self.params = params
+        self.nx, self.ny = params.nx, params.ny
+        self.dtype = torch.float32 if params.precision == MIXED else torch.float64
+
+    @classmethod
+    def from_run(cls, run, precision=FP64) -> "Solver":
+        return cls(make_params(run.nx, run.ny, run.dx, run.dy, run.dt, run.tau, run.gamma, run.v,
+                               run.eta, run.bc_x, run.bc_y, precision))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().cdbm_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- buffers -----------------------------------------------------------
+    def empty_f(self) -> torch.Tensor:
+        return torch.empty((16, self.ny, self.nx), dtype=self.dtype, device="cuda")
+
+    def empty_field(self, *lead) -> torch.Tensor:
+        return torch.empty(tuple(lead) + (self.ny, self.nx), dtype=torch.float64, device="cuda")
+
+    def _field(self, a) -> torch.Tensor:
+        t = torch.as_tensor(a, dtype=torch.float64)
+        return t.to("cuda").contiguous().reshape(self.ny, self.nx)
+
+    # -- forward -----------------------------------------------------------
+    def init(self, rho, ux, uy, T, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        fs = [self._field(a) for a in (rho, ux, uy, T)]
+        out = self.empty_f() if out is None else out
+        _check(load().cdbm_init(self._h, *[_ptr(a) for a in fs], _ptr(out), _stream()), "cdbm_init")
+        return out
+
+    def step(self, f_in: torch.Tensor, f_out: Optional[torch.Tensor] = None,
+             nsteps: int = 1) -> torch.Tensor:
+        f_out = self.empty_f() if f_out is None else f_out
+        _check(load().cdbm_step(self._h, _ptr(f_in), _ptr(f_out), int(nsteps), _stream()), "cdbm_step")
+        return f_out
+
+    def moments(self, f: torch.Tensor) -> Tuple[torch.Tensor, ...]:
+        outs = [self.empty_field() for _ in range(4)]
+        _check(load().cdbm_moments(self._h, _ptr(f), *[_ptr(o) for o in outs], _stream()),
+               "cdbm_moments")
+        return tuple(outs)
+
+    def tne(self, f: torch.Tensor) -> torch.Tensor:
+        out = self.empty_field(12)
+        _check(load().cdbm_tne(self._h, _ptr(f), _ptr(out), _stream()), "cdbm_tne")
+        return out
+
+    def totals(self, f: torch.Tensor) -> torch.Tensor:
+        out = torch.empty(4, dtype=torch.float64, device="cuda")
+        _check(load().cdbm_conserved_totals(self._h, _ptr(f), _ptr(out), _stream()),
+               "cdbm_conserved_totals")
+        return out
+
+    # -- reverse mode --------------------------------------------------------
+    def step_adjoint(self, f_n: torch.Tensor, lam_np1: torch.Tensor,
+                     lam_n: Optional[torch.Tensor] = None,
+                     dtau: Optional[torch.Tensor] = None):
+        lam_n = self.empty_f() if lam_n is None else lam_n
+        dtau = torch.zeros(1, dtype=torch.float64, device="cuda") if dtau is None else dtau
+        _check(load().cdbm_step_adjoint(self._h, _ptr(f_n), _ptr(lam_np1), _ptr(lam_n), _ptr(dtau),
+                                        _stream()), "cdbm_step_adjoint")
+        return lam_n, dtau
+
+    def init_adjoint(self, rho, ux, uy, T, lam_f0: torch.Tensor):
+        fs = [self._field(a) for a in (rho, ux, uy, T)]
+        outs = [self.empty_field() for _ in range(4)]
+        _check(load().cdbm_init_adjoint(self._h, *[_ptr(a) for a in fs], _ptr(lam_f0),
+                                        *[_ptr(o) for o in outs], _stream()), "cdbm_init_adjoint")
+        return tuple(outs)
+
+    def moments_adjoint(self, f: torch.Tensor, g_rho, g_ux, g_uy, g_T,
+                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        gs = [self._field(g) for g in (g_rho, g_ux, g_uy, g_T)]
+        out = self.empty_f() if out is None else out
+        _check(load().cdbm_moments_adjoint(self._h, _ptr(f), *[_ptr(g) for g in gs], _ptr(out),
+                                           _stream()), "cdbm_moments_adjoint")
+        return out
+
+
+class Batch:
+    """Independent grids advanced together (cdbm_batch_*)."""
+
+    def __init__(self, params: Sequence[Params]):
+        lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the CDBM library needs a GPU")
+        n = len(params)
+        arr = (Params * n)(*params)
+        sizes = [16 * p.nx * p.ny for p in params]
+        offs = [0]
+        for s in sizes[:-1]:
+            offs.append(offs[-1] + s)
+        self.offsets = offs
+        self.sizes = sizes
+        self.total = sum(sizes)
+        self.params = list(params)
+        self.dtype = torch.float32 if params[0].precision == MIXED else torch.float64
+        c_offs = (ctypes.c_int64 * n)(*offs)
+        b = _vp()
+        _check(lib.cdbm_batch_create(arr, n, c_offs, ctypes.byref(b)), "cdbm_batch_create")
+        self._b = b
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            load().cdbm_batch_destroy(self._b)
+            self._b = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty_f(self) -> torch.Tensor:
+        return torch.empty(self.total, dtype=self.dtype, device="cuda")
+
+    def view(self, f: torch.Tensor, k: int) -> torch.Tensor:
+        p = self.params[k]
+        return f[self.offsets[k]:self.offsets[k] + self.sizes[k]].view(16, p.ny, p.nx)
+
+    def init(self, fields: Sequence[Tuple], out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        cat = [torch.cat([torch.as_tensor(fl[q], dtype=torch.float64).reshape(-1) for fl in fields])
+               .to("cuda") for q in range(4)]
+        out = self.empty_f() if out is None else out
+        _check(load().cdbm_batch_init(self._b, *[_ptr(c) for c in cat], _ptr(out), _stream()),
+               "cdbm_batch_init")
+        return out
+
+    def step(self, f_in: torch.Tensor, f_out: Optional[torch.Tensor] = None,
+             nsteps: int = 1) -> torch.Tensor:
+        f_out = self.empty_f() if f_out is None else f_out
+        _check(load().cdbm_batch_step(self._b, _ptr(f_in), _ptr(f_out), int(nsteps), _stream()),
+               "cdbm_batch_step")
+        return f_out

@@ -1,0 +1,283 @@
+// C ABI of the CDBM library (include/cdbm.h): handle lifetime, argument
+// checks, buffer ping-pong, graph capture of the step loop.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cdbm.h"
+#include "launch.hpp"
+#include "model.hpp"
+
+using cdbm::KParams;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+    g_err = buf;
+    return CDBM_EHIP;
+}
+
+constexpr int REDUCE_BLOCKS = 1024;
+constexpr int GRAPH_STEPS = 32;   // steps per captured graph (an even number)
+
+}  // namespace
+
+struct cdbm_handle {
+    cdbm_params p;
+    KParams k;
+    int device = 0;
+    int64_t cells = 0;
+    size_t elem = 8;
+    size_t fbytes = 0;
+    void* scratch = nullptr;    // f-sized ping-pong buffer
+    void* stage = nullptr;      // f-sized buffer for the adjoint's stage-1 state
+    void* lam_mid = nullptr;    // f-sized buffer for the adjoint's intermediate product
+    double* partials = nullptr; // reduction partials
+    int* flag = nullptr;        // device flag of the field check
+    // graph of GRAPH_STEPS steps ping-ponging between gout and scratch
+    hipGraphExec_t gexec = nullptr;
+    void* gout = nullptr;
+};
+
+namespace {
+
+bool mixed(const cdbm_handle* h) { return h->p.precision == CDBM_MIXED; }
+
+hipError_t step_once(const cdbm_handle* h, const void* fin, void* fout, hipStream_t st) {
+    return mixed(h) ? cdbm::launch_step_fused<float>(fin, fout, h->k, st)
+                    : cdbm::launch_step_fused<double>(fin, fout, h->k, st);
+}
+
+int check_device(const cdbm_handle* h) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != h->device) return fail(CDBM_EINVAL, "handle was created on another device");
+    return CDBM_OK;
+}
+
+int check_fields(cdbm_handle* h, const double* rho, const double* ux, const double* uy,
+                 const double* T, hipStream_t st) {
+    if (!rho || !ux || !uy || !T) return fail(CDBM_EINVAL, "null field pointer");
+    hipError_t e = hipMemsetAsync(h->flag, 0, sizeof(int), st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    e = cdbm::launch_check_fields(rho, ux, uy, T, h->cells, h->flag, st);
+    if (e != hipSuccess) return hip_fail(e, "field check launch");
+    int bad = 0;
+    e = hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (bad) return fail(CDBM_ENONPHYS, "rho <= 0, T <= 0 or a non-finite value in the fields");
+    return CDBM_OK;
+}
+
+int ensure_buffer(cdbm_handle* h, void** buf) {
+    if (*buf) return CDBM_OK;
+    hipError_t e = hipMalloc(buf, h->fbytes);
+    if (e != hipSuccess) {
+        *buf = nullptr;
+        return fail(CDBM_ENOMEM, "hipMalloc of an f-sized buffer failed");
+    }
+    return CDBM_OK;
+}
+
+void drop_graph(cdbm_handle* h) {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    h->gout = nullptr;
+}
+
+// Capture GRAPH_STEPS steps f_out -> scratch -> f_out ... -> f_out.
+int capture_graph(cdbm_handle* h, void* fout, hipStream_t st) {
+    drop_graph(h);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    for (int s = 0; s < GRAPH_STEPS; ++s) {
+        const void* src = (s % 2 == 0) ? fout : h->scratch;
+        void* dst = (s % 2 == 0) ? h->scratch : fout;
+        hipError_t le = step_once(h, src, dst, st);
+        if (le != hipSuccess) {
+            (void)hipStreamEndCapture(st, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(le, "step launch during capture");
+        }
+    }
+    e = hipStreamEndCapture(st, &graph);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        h->gexec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    h->gout = fout;
+    return CDBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cdbm_last_error(void) { return g_err.c_str(); }
+
+int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
+    if (!p || !out) return fail(CDBM_EINVAL, "null argument");
+    *out = nullptr;
+    auto* h = new (std::nothrow) cdbm_handle();
+    if (!h) return fail(CDBM_ENOMEM, "host allocation failed");
+    h->p = *p;
+    std::string err;
+    int rc = cdbm::build_params(*p, h->k, err);
+    if (rc != CDBM_OK) {
+        delete h;
+        return fail(rc, err);
+    }
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipGetDevice");
+    }
+    h->cells = (int64_t)p->nx * p->ny;
+    h->elem = mixed(h) ? sizeof(float) : sizeof(double);
+    h->fbytes = (size_t)cdbm::NV * (size_t)h->cells * h->elem;
+    if (ensure_buffer(h, &h->scratch) != CDBM_OK ||
+        hipMalloc(&h->partials, sizeof(double) * 4 * REDUCE_BLOCKS) != hipSuccess ||
+        hipMalloc(&h->flag, sizeof(int)) != hipSuccess) {
+        cdbm_destroy(h);
+        return fail(CDBM_ENOMEM, "device allocation failed");
+    }
+    *out = h;
+    return CDBM_OK;
+}
+
+int cdbm_destroy(cdbm_handle* h) {
+    if (!h) return CDBM_OK;
+    (void)hipDeviceSynchronize();
+    drop_graph(h);
+    if (h->scratch) (void)hipFree(h->scratch);
+    if (h->stage) (void)hipFree(h->stage);
+    if (h->lam_mid) (void)hipFree(h->lam_mid);
+    if (h->partials) (void)hipFree(h->partials);
+    if (h->flag) (void)hipFree(h->flag);
+    delete h;
+    return CDBM_OK;
+}
+
+int cdbm_get_params(const cdbm_handle* h, cdbm_params* out) {
+    if (!h || !out) return fail(CDBM_EINVAL, "null argument");
+    *out = h->p;
+    return CDBM_OK;
+}
+
+int cdbm_init(cdbm_handle* h, const double* rho, const double* ux, const double* uy,
+              const double* T, void* f_out, void* stream) {
+    if (!h || !f_out) return fail(CDBM_EINVAL, "null argument");
+    int rc = check_device(h);
+    if (rc != CDBM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    rc = check_fields(h, rho, ux, uy, T, st);
+    if (rc != CDBM_OK) return rc;
+    hipError_t e = mixed(h) ? cdbm::launch_init<float>(rho, ux, uy, T, f_out, h->k, st)
+                            : cdbm::launch_init<double>(rho, ux, uy, T, f_out, h->k, st);
+    return e == hipSuccess ? CDBM_OK : hip_fail(e, "init launch");
+}
+
+int cdbm_step(cdbm_handle* h, const void* f_in, void* f_out, int32_t nsteps, void* stream) {
+    if (!h || !f_in || !f_out) return fail(CDBM_EINVAL, "null argument");
+    if (nsteps < 0) return fail(CDBM_EINVAL, "nsteps must be >= 0");
+    const char* a = (const char*)f_in;
+    const char* b = (const char*)f_out;
+    if (a < b + h->fbytes && b < a + h->fbytes) return fail(CDBM_EINVAL, "f_in and f_out overlap");
+    int rc = check_device(h);
+    if (rc != CDBM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (nsteps == 0) {
+        hipError_t e = hipMemcpyAsync(f_out, f_in, h->fbytes, hipMemcpyDeviceToDevice, st);
+        return e == hipSuccess ? CDBM_OK : hip_fail(e, "hipMemcpyAsync");
+    }
+    // Destinations alternate between f_out and scratch and end on f_out.
+    const void* src = f_in;
+    int remaining = nsteps;
+    hipError_t e;
+    if (nsteps % 2 == 1) {
+        e = step_once(h, src, f_out, st);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        --remaining;
+    } else {
+        e = step_once(h, src, h->scratch, st);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        e = step_once(h, h->scratch, f_out, st);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        remaining -= 2;
+    }
+    // remaining is even; the state is in f_out.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool can_graph = st != nullptr && hipStreamIsCapturing(st, &cs) == hipSuccess &&
+                           cs == hipStreamCaptureStatusNone;
+    if (can_graph && remaining >= GRAPH_STEPS) {
+        if (!h->gexec || h->gout != f_out) {
+            rc = capture_graph(h, f_out, st);
+            if (rc != CDBM_OK) return rc;
+        }
+        while (remaining >= GRAPH_STEPS) {
+            e = hipGraphLaunch(h->gexec, st);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+            remaining -= GRAPH_STEPS;
+        }
+    }
+    while (remaining > 0) {
+        e = step_once(h, f_out, h->scratch, st);
+        if (e == hipSuccess) e = step_once(h, h->scratch, f_out, st);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        remaining -= 2;
+    }
+    return CDBM_OK;
+}
+
+int cdbm_moments(cdbm_handle* h, const void* f, double* rho, double* ux, double* uy, double* T,
+                 void* stream) {
+    if (!h || !f || !rho || !ux || !uy || !T) return fail(CDBM_EINVAL, "null argument");
+    int rc = check_device(h);
+    if (rc != CDBM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = mixed(h) ? cdbm::launch_moments<float>(f, rho, ux, uy, T, h->k, st)
+                            : cdbm::launch_moments<double>(f, rho, ux, uy, T, h->k, st);
+    return e == hipSuccess ? CDBM_OK : hip_fail(e, "moments launch");
+}
+
+int cdbm_tne(cdbm_handle* h, const void* f, double* out12, void* stream) {
+    if (!h || !f || !out12) return fail(CDBM_EINVAL, "null argument");
+    int rc = check_device(h);
+    if (rc != CDBM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = mixed(h) ? cdbm::launch_tne<float>(f, out12, h->k, st)
+                            : cdbm::launch_tne<double>(f, out12, h->k, st);
+    return e == hipSuccess ? CDBM_OK : hip_fail(e, "tne launch");
+}
+
+int cdbm_conserved_totals(cdbm_handle* h, const void* f, double* out4, void* stream) {
+    if (!h || !f || !out4) return fail(CDBM_EINVAL, "null argument");
+    int rc = check_device(h);
+    if (rc != CDBM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = mixed(h)
+                       ? cdbm::launch_totals<float>(f, h->partials, REDUCE_BLOCKS, out4, h->k, st)
+                       : cdbm::launch_totals<double>(f, h->partials, REDUCE_BLOCKS, out4, h->k, st);
+    return e == hipSuccess ? CDBM_OK : hip_fail(e, "totals launch");
+}
+
+}  // extern "C"

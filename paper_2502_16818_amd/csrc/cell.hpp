@@ -1,0 +1,203 @@
+// Per-cell device arithmetic of the CDBM step, shared by every kernel.
+//
+// Equilibrium (Eqs. (4)-(7)).  For a cell with distributions f_i:
+//   1. parity combinations g of each group of four f_i (sums and differences
+//      of opposite velocities);
+//   2. conserved moments rho, j, 2E from g, then u = j / rho and
+//      T = (2E / rho - |u|^2) / (D + I)   (energy row of Eq. (4));
+//   3. raw Maxwellian moments m^eq / rho in the parity blocks (the exact
+//      central-to-raw shift of the central moments of Eq. (5));
+//   4. h = rho * Binv m-hat per block, with the block inverses of the moment
+//      matrix at u = 0 (built on the host; rows pre-scaled by 1/2 or 1/4);
+//   5. unpack h into the 16 f_i^eq with additions.
+// All of it runs in double, in every precision mode.
+//
+// NND (Eqs. (12)-(20)).  For a velocity component v > 0 only f^+ = v f is
+// nonzero and the flux difference H(j+1/2) - H(j-1/2) reduces to
+//   v [ (f_j - f_{j-1}) + (minmod(f_{j+1}-f_j, f_j-f_{j-1})
+//                          - minmod(f_j-f_{j-1}, f_{j-1}-f_{j-2})) / 2 ],
+// and for v < 0 (only f^- nonzero) to the mirror image
+//   v [ (f_{j+1} - f_j) - (minmod(f_{j+2}-f_{j+1}, f_{j+1}-f_j)
+//                          - minmod(f_{j+1}-f_j, f_j-f_{j-1})) / 2 ].
+// minmod of Eq. (16) equals the median of (X, Y, 0).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "model.hpp"
+
+namespace cdbm {
+
+__device__ __forceinline__ float minmod(float X, float Y) {
+    return __builtin_amdgcn_fmed3f(X, Y, 0.0f);
+}
+__device__ __forceinline__ double minmod(double X, double Y) {
+    return fmax(fmin(X, Y), fmin(fmax(X, Y), 0.0));
+}
+
+// D for a positive component (stencil j-2 .. j+1) and a negative one (j-1 .. j+2).
+template <typename R>
+__device__ __forceinline__ R nnd_pos(R m2, R m1, R c0, R p1) {
+    const R d0 = c0 - m1;
+    return d0 + R(0.5) * (minmod(p1 - c0, d0) - minmod(d0, m1 - m2));
+}
+template <typename R>
+__device__ __forceinline__ R nnd_neg(R m1, R c0, R p1, R p2) {
+    const R d1 = p1 - c0;
+    return d1 - R(0.5) * (minmod(p2 - p1, d1) - minmod(d1, c0 - m1));
+}
+
+struct Parity {
+    double ee[6], oe[4], eo[4], oo[2];
+};
+
+// Parity combinations of the 16 distributions (velocity order of model.hpp).
+__device__ __forceinline__ void to_parity(const double f[NV], Parity& g) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int a = 8 * q;       // axis group (a or c)
+        const int d = 8 * q + 4;   // diagonal group (b or d)
+        g.ee[3 * q + 0] = f[a + 0] + f[a + 2];
+        g.ee[3 * q + 1] = f[a + 1] + f[a + 3];
+        g.oe[2 * q + 0] = f[a + 0] - f[a + 2];
+        g.eo[2 * q + 0] = f[a + 1] - f[a + 3];
+        const double s01 = f[d + 0] + f[d + 1], s23 = f[d + 2] + f[d + 3];
+        const double d01 = f[d + 0] - f[d + 1], d23 = f[d + 2] - f[d + 3];
+        g.ee[3 * q + 2] = s01 + s23;
+        g.oe[2 * q + 1] = d01 - d23;
+        g.eo[2 * q + 1] = s01 - s23;
+        g.oo[q] = d01 + d23;
+    }
+}
+
+struct Macro {
+    double rho, ux, uy, T;
+};
+
+__device__ __forceinline__ Macro macro_from_parity(const Parity& g, const KParams& K, double a) {
+    const double rho = ((g.ee[0] + g.ee[1]) + (g.ee[2] + g.ee[3])) + (g.ee[4] + g.ee[5]);
+    double jx = 0.0, jy = 0.0, e2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        jx = fma(K.jx[c], g.oe[c], jx);
+        jy = fma(K.jy[c], g.eo[c], jy);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e2 = fma(K.en[c], g.ee[c], e2);
+    const double inv = 1.0 / rho;
+    Macro m;
+    m.rho = rho;
+    m.ux = jx * inv;
+    m.uy = jy * inv;
+    m.T = (e2 * inv - (m.ux * m.ux + m.uy * m.uy)) / a;
+    return m;
+}
+
+// f^eq of the state m (Eq. (7)), through the raw moments and the shared
+// parity-block inverses; a = D + I.
+__device__ __forceinline__ void equilibrium(const Macro& m, const KParams& K, double a,
+                                            double feq[NV]) {
+    const double ux = m.ux, uy = m.uy, T = m.T;
+    const double ux2 = ux * ux, uy2 = uy * uy, u2 = ux2 + uy2, uxy = ux * uy;
+    const double aT = a * T;
+    const double A2 = u2 + aT + 2.0 * T;   // u^2 + (D+I+2) T
+    const double A4 = A2 + 2.0 * T;        // u^2 + (D+I+4) T
+    // raw moments / rho, rows (1,4,5,7,14,16), (2,8,10,12), (3,9,11,13), (6,15)
+    const double mee[6] = {1.0, u2 + aT, ux2 + T, uy2 + T, ux2 * A4 + T * A2, uy2 * A4 + T * A2};
+    const double moe[4] = {ux, ux * A2, ux * (ux2 + 3.0 * T), ux * (uy2 + T)};
+    const double meo[4] = {uy, uy * A2, uy * (ux2 + T), uy * (uy2 + 3.0 * T)};
+    const double moo[2] = {uxy, uxy * A4};
+    double hee[6], hoe[4], heo[4], hoo[2];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        double s = K.iee[r][0];
+#pragma unroll
+        for (int c = 1; c < 6; ++c) s = fma(K.iee[r][c], mee[c], s);
+        hee[r] = m.rho * s;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        double so = 0.0, se = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            so = fma(K.ioe[r][c], moe[c], so);
+            se = fma(K.ieo[r][c], meo[c], se);
+        }
+        hoe[r] = m.rho * so;
+        heo[r] = m.rho * se;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) hoo[r] = m.rho * fma(K.ioo[r][0], moo[0], K.ioo[r][1] * moo[1]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int a = 8 * q, d = 8 * q + 4;
+        feq[a + 0] = hee[3 * q + 0] + hoe[2 * q];
+        feq[a + 2] = hee[3 * q + 0] - hoe[2 * q];
+        feq[a + 1] = hee[3 * q + 1] + heo[2 * q];
+        feq[a + 3] = hee[3 * q + 1] - heo[2 * q];
+        const double p = hee[3 * q + 2] + heo[2 * q + 1], n = hee[3 * q + 2] - heo[2 * q + 1];
+        const double r = hoe[2 * q + 1] + hoo[q], s = hoe[2 * q + 1] - hoo[q];
+        feq[d + 0] = p + r;
+        feq[d + 1] = p - r;
+        feq[d + 2] = n - s;
+        feq[d + 3] = n + s;
+    }
+}
+
+// Boundary index map for a neighbour offset: periodic wrap or clamp.
+__device__ __forceinline__ int wrap_or_clamp(int i, int n, int bc) {
+    if (bc == CDBM_PERIODIC) {
+        i %= n;
+        return i < 0 ? i + n : i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+template <typename S>
+__device__ __forceinline__ S coef_x(const KParams& K, int i);
+template <>
+__device__ __forceinline__ float coef_x<float>(const KParams& K, int i) { return K.cxf[i]; }
+template <>
+__device__ __forceinline__ double coef_x<double>(const KParams& K, int i) { return K.cx[i]; }
+template <typename S>
+__device__ __forceinline__ S coef_y(const KParams& K, int i);
+template <>
+__device__ __forceinline__ float coef_y<float>(const KParams& K, int i) { return K.cyf[i]; }
+template <>
+__device__ __forceinline__ double coef_y<double>(const KParams& K, int i) { return K.cy[i]; }
+
+// One Runge-Kutta stage at one cell.  `ld(i, ox, oy)` returns f_i at the
+// cell offset by (ox, oy) with boundary conditions applied.  Writes
+//   out_i = f_i + dt (-v_i . grad f_i) - (dt / tau) (f_i - f_i^eq)
+// which is f + dt L(f); the caller combines stages.
+template <typename S, class Ld>
+__device__ __forceinline__ void stage_cell(const Ld& ld, const KParams& K, S out[NV]) {
+    S f[NV];
+    double fd[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        f[i] = ld(i, 0, 0);
+        fd[i] = (double)f[i];
+    }
+    Parity g;
+    to_parity(fd, g);
+    const Macro m = macro_from_parity(g, K, K.a);
+    double feq[NV];
+    equilibrium(m, K, K.a, feq);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        S adv = S(0);
+        if (SX[i] > 0)
+            adv = coef_x<S>(K, i) * nnd_pos<S>(ld(i, -2, 0), ld(i, -1, 0), f[i], ld(i, 1, 0));
+        else if (SX[i] < 0)
+            adv = coef_x<S>(K, i) * nnd_neg<S>(ld(i, -1, 0), f[i], ld(i, 1, 0), ld(i, 2, 0));
+        if (SY[i] > 0)
+            adv += coef_y<S>(K, i) * nnd_pos<S>(ld(i, 0, -2), ld(i, 0, -1), f[i], ld(i, 0, 1));
+        else if (SY[i] < 0)
+            adv += coef_y<S>(K, i) * nnd_neg<S>(ld(i, 0, -1), f[i], ld(i, 0, 1), ld(i, 0, 2));
+        const S coll = (S)(K.z * (fd[i] - feq[i]));
+        out[i] = f[i] + (adv - coll);
+    }
+}
+
+}  // namespace cdbm

@@ -1,0 +1,274 @@
+// Point-wise and simple stencil kernels of the CDBM library: initial
+// equilibrium, field checks, macroscopic moments, nonequilibrium measures,
+// conserved totals and the unfused Runge-Kutta stage.
+#include <hip/hip_runtime.h>
+
+#include "cell.hpp"
+#include "launch.hpp"
+
+namespace cdbm {
+
+namespace {
+
+// f = f^eq(rho, u, T) per cell (the initial condition of Sec. 3).
+template <typename S>
+__global__ void __launch_bounds__(256) k_init(const double* __restrict__ rho,
+                                              const double* __restrict__ ux,
+                                              const double* __restrict__ uy,
+                                              const double* __restrict__ T, S* __restrict__ f,
+                                              KParams K, int64_t cells) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    Macro m{rho[c], ux[c], uy[c], T[c]};
+    double feq[NV];
+    equilibrium(m, K, K.a, feq);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) f[i * cells + c] = (S)feq[i];
+}
+
+// bad |= 1 if rho <= 0, T <= 0 or any field value is not finite.
+__global__ void __launch_bounds__(256) k_check_fields(const double* __restrict__ rho,
+                                                      const double* __restrict__ ux,
+                                                      const double* __restrict__ uy,
+                                                      const double* __restrict__ T,
+                                                      int64_t cells, int* __restrict__ bad) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const double r = rho[c], a = ux[c], b = uy[c], t = T[c];
+    const bool ok = isfinite(r) && isfinite(a) && isfinite(b) && isfinite(t) && r > 0.0 && t > 0.0;
+    if (!ok) atomicOr(bad, 1);
+}
+
+template <typename S>
+__device__ __forceinline__ void load_cell(const S* __restrict__ f, int64_t cells, int64_t c,
+                                          double fd[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) fd[i] = (double)f[i * cells + c];
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_moments(const S* __restrict__ f, double* __restrict__ rho,
+                                                 double* __restrict__ ux, double* __restrict__ uy,
+                                                 double* __restrict__ T, KParams K, int64_t cells) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    double fd[NV];
+    load_cell(f, cells, c, fd);
+    Parity g;
+    to_parity(fd, g);
+    const Macro m = macro_from_parity(g, K, K.a);
+    rho[c] = m.rho;
+    ux[c] = m.ux;
+    uy[c] = m.uy;
+    T[c] = m.T;
+}
+
+// Eqs. (8)-(11): sum_i (f_i - f_i^eq) Psi_r(v_i - u), rows r = 5..16.
+template <typename S>
+__global__ void __launch_bounds__(256) k_tne(const S* __restrict__ f, double* __restrict__ out,
+                                             KParams K, int64_t cells) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    double fd[NV];
+    load_cell(f, cells, c, fd);
+    Parity g;
+    to_parity(fd, g);
+    const Macro m = macro_from_parity(g, K, K.a);
+    double feq[NV];
+    equilibrium(m, K, K.a, feq);
+    double acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const double d = fd[i] - feq[i];
+        const double cx = K.vx[i] - m.ux, cy = K.vy[i] - m.uy;
+        const double e = cx * cx + cy * cy + K.eta2[i];
+        const double xx = cx * cx, xy = cx * cy, yy = cy * cy;
+        acc[0] = fma(d, xx, acc[0]);
+        acc[1] = fma(d, xy, acc[1]);
+        acc[2] = fma(d, yy, acc[2]);
+        acc[3] = fma(d, e * cx, acc[3]);
+        acc[4] = fma(d, e * cy, acc[4]);
+        acc[5] = fma(d, xx * cx, acc[5]);
+        acc[6] = fma(d, xx * cy, acc[6]);
+        acc[7] = fma(d, xy * cy, acc[7]);
+        acc[8] = fma(d, yy * cy, acc[8]);
+        acc[9] = fma(d, e * xx, acc[9]);
+        acc[10] = fma(d, e * xy, acc[10]);
+        acc[11] = fma(d, e * yy, acc[11]);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) out[k * cells + c] = acc[k];
+}
+
+// Per-block partial sums of (rho, j_x, j_y, 2E); block count is fixed.
+template <typename S>
+__global__ void __launch_bounds__(256) k_totals_partial(const S* __restrict__ f, KParams K,
+                                                        int64_t cells, double* __restrict__ part) {
+    __shared__ double red[4][256];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        double fd[NV];
+        load_cell(f, cells, c, fd);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            acc[0] += fd[i];
+            acc[1] = fma(fd[i], K.vx[i], acc[1]);
+            acc[2] = fma(fd[i], K.vy[i], acc[2]);
+            acc[3] = fma(fd[i], K.vx[i] * K.vx[i] + K.vy[i] * K.vy[i] + K.eta2[i], acc[3]);
+        }
+    }
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// out[k] = sum over blocks of part[b*4 + k], in a fixed order.
+__global__ void __launch_bounds__(256) k_sum_partials(const double* __restrict__ part, int nblocks,
+                                                      int ncomp, double* __restrict__ out) {
+    __shared__ double red[256];
+    for (int k = 0; k < ncomp; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += part[b * ncomp + k];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = red[0];
+        __syncthreads();
+    }
+}
+
+// Global-memory neighbour access with boundary conditions, for the unfused stage.
+template <typename S>
+struct GlobalLd {
+    const S* __restrict__ f;
+    int64_t cells;
+    int nx;
+    int xs[5];   // source columns of offsets -2..2
+    int ys[5];   // source rows of offsets -2..2
+    __device__ __forceinline__ S operator()(int i, int ox, int oy) const {
+        return f[i * cells + (int64_t)ys[oy + 2] * nx + xs[ox + 2]];
+    }
+};
+
+// One Runge-Kutta stage without fusion:
+//   STAGE2 == false:  out = f + dt L(f)
+//   STAGE2 == true:   out = base / 2 + (f + dt L(f)) / 2
+template <typename S, bool STAGE2>
+__global__ void __launch_bounds__(256) k_stage(const S* __restrict__ fin, const S* __restrict__ base,
+                                               S* __restrict__ fout, KParams K) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= K.nx || y >= K.ny) return;
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    GlobalLd<S> ld;
+    ld.f = fin;
+    ld.cells = cells;
+    ld.nx = K.nx;
+#pragma unroll
+    for (int o = -2; o <= 2; ++o) {
+        ld.xs[o + 2] = wrap_or_clamp(x + o, K.nx, K.bcx);
+        ld.ys[o + 2] = wrap_or_clamp(y + o, K.ny, K.bcy);
+    }
+    S out[NV];
+    stage_cell<S>(ld, K, out);
+    const int64_t c = (int64_t)y * K.nx + x;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        S v = out[i];
+        if (STAGE2) v = S(0.5) * base[i * cells + c] + S(0.5) * v;
+        fout[i * cells + c] = v;
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+template <typename S>
+hipError_t launch_init(const double* rho, const double* ux, const double* uy, const double* T,
+                       void* f, const KParams& K, hipStream_t st) {
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    hipLaunchKernelGGL(k_init<S>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, rho, ux, uy, T,
+                       (S*)f, K, cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_fields(const double* rho, const double* ux, const double* uy,
+                               const double* T, int64_t cells, int* bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_fields, dim3(blocks_for(cells, 256)), dim3(256), 0, st, rho, ux, uy,
+                       T, cells, bad);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_moments(const void* f, double* rho, double* ux, double* uy, double* T,
+                          const KParams& K, hipStream_t st) {
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    hipLaunchKernelGGL(k_moments<S>, dim3(blocks_for(cells, 256)), dim3(256), 0, st,
+                       (const S*)f, rho, ux, uy, T, K, cells);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_tne(const void* f, double* out12, const KParams& K, hipStream_t st) {
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    hipLaunchKernelGGL(k_tne<S>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, (const S*)f,
+                       out12, K, cells);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_totals(const void* f, double* partials, int nblocks, double* out4,
+                         const KParams& K, hipStream_t st) {
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    hipLaunchKernelGGL(k_totals_partial<S>, dim3(nblocks), dim3(256), 0, st, (const S*)f, K,
+                       cells, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partials, nblocks, 4, out4);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double* part, int nblocks, int ncomp, double* out,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, part, nblocks, ncomp, out);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_stage(const void* fin, const void* base, void* fout, bool stage2,
+                        const KParams& K, hipStream_t st) {
+    const dim3 grid(blocks_for(K.nx, 64), blocks_for(K.ny, 4));
+    if (stage2)
+        hipLaunchKernelGGL((k_stage<S, true>), grid, dim3(256), 0, st, (const S*)fin,
+                           (const S*)base, (S*)fout, K);
+    else
+        hipLaunchKernelGGL((k_stage<S, false>), grid, dim3(256), 0, st, (const S*)fin,
+                           (const S*)base, (S*)fout, K);
+    return hipGetLastError();
+}
+
+#define CDBM_INSTANTIATE(S)                                                                     \
+    template hipError_t launch_init<S>(const double*, const double*, const double*,            \
+                                       const double*, void*, const KParams&, hipStream_t);     \
+    template hipError_t launch_moments<S>(const void*, double*, double*, double*, double*,     \
+                                          const KParams&, hipStream_t);                        \
+    template hipError_t launch_tne<S>(const void*, double*, const KParams&, hipStream_t);      \
+    template hipError_t launch_totals<S>(const void*, double*, int, double*, const KParams&,   \
+                                         hipStream_t);                                         \
+    template hipError_t launch_stage<S>(const void*, const void*, void*, bool, const KParams&, \
+                                        hipStream_t);
+CDBM_INSTANTIATE(float)
+CDBM_INSTANTIATE(double)
+#undef CDBM_INSTANTIATE
+
+}  // namespace cdbm

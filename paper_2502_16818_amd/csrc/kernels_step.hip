@@ -1,0 +1,70 @@
+// Fused CDBM time step on one grid: a persistent launch whose blocks each
+// take an equal, contiguous share of the grid's (strip, row) sequence, so
+// that every block streams down as few strips as possible and the work is
+// balanced to within a few rows.
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "step_fused.hpp"
+
+namespace cdbm {
+
+namespace {
+
+template <typename S>
+__global__ void __launch_bounds__(FUSED_NT) k_step_fused(const S* __restrict__ fin,
+                                                         S* __restrict__ fout, KParams K) {
+    __shared__ S F0[FUSED_SLOTS * NV * FUSED_W0];
+    __shared__ S F1[FUSED_SLOTS * NV * FUSED_W1];
+    const GridC<S> G = grid_from<S>(K);
+    const int nstrips = (K.nx + FUSED_TX - 1) / FUSED_TX;
+    const int64_t work = (int64_t)nstrips * K.ny;
+    const int64_t u1 = work * (blockIdx.x + 1) / gridDim.x;
+    int64_t u = work * blockIdx.x / gridDim.x;
+    while (u < u1) {
+        const int s = (int)(u / K.ny);
+        const int ya = (int)(u - (int64_t)s * K.ny);
+        const int yb = (int)min((int64_t)K.ny, (int64_t)ya + (u1 - u));
+        fused_strip<S>(fin, fout, K, G, s * FUSED_TX, ya, yb, F0, F1);
+        u += yb - ya;
+    }
+}
+
+template <typename S>
+int fused_grid_blocks(const KParams& K) {
+    static int per_cu = -1, cus = -1;
+    if (per_cu < 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 256;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+        cus = prop.multiProcessorCount;
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_fused<S>, FUSED_NT, 0) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    const int nstrips = (K.nx + FUSED_TX - 1) / FUSED_TX;
+    const int64_t work = (int64_t)nstrips * K.ny;
+    int64_t g = (int64_t)per_cu * cus;
+    // each block should stream at least ~16 rows so the pipeline warm-up stays small
+    const int64_t cap = (work + 15) / 16;
+    if (g > cap) g = cap;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+template <typename S>
+hipError_t launch_step_fused(const void* fin, void* fout, const KParams& K, hipStream_t st) {
+    const int g = fused_grid_blocks<S>(K);
+    hipLaunchKernelGGL(k_step_fused<S>, dim3(g), dim3(FUSED_NT), 0, st, (const S*)fin, (S*)fout, K);
+    return hipGetLastError();
+}
+
+template hipError_t launch_step_fused<float>(const void*, void*, const KParams&, hipStream_t);
+template hipError_t launch_step_fused<double>(const void*, void*, const KParams&, hipStream_t);
+
+}  // namespace cdbm

@@ -1,0 +1,57 @@
+// Host-side launchers of the CDBM kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "model.hpp"
+
+namespace cdbm {
+
+template <typename S>
+hipError_t launch_init(const double* rho, const double* ux, const double* uy, const double* T,
+                       void* f, const KParams& K, hipStream_t st);
+hipError_t launch_check_fields(const double* rho, const double* ux, const double* uy,
+                               const double* T, int64_t cells, int* bad, hipStream_t st);
+template <typename S>
+hipError_t launch_moments(const void* f, double* rho, double* ux, double* uy, double* T,
+                          const KParams& K, hipStream_t st);
+template <typename S>
+hipError_t launch_tne(const void* f, double* out12, const KParams& K, hipStream_t st);
+template <typename S>
+hipError_t launch_totals(const void* f, double* partials, int nblocks, double* out4,
+                         const KParams& K, hipStream_t st);
+hipError_t launch_sum_partials(const double* part, int nblocks, int ncomp, double* out,
+                               hipStream_t st);
+template <typename S>
+hipError_t launch_stage(const void* fin, const void* base, void* fout, bool stage2,
+                        const KParams& K, hipStream_t st);
+
+// Fused two-stage step (kernels_step.hip).
+template <typename S>
+hipError_t launch_step_fused(const void* fin, void* fout, const KParams& K, hipStream_t st);
+
+// Adjoint (kernels_adjoint.hip).
+template <typename S>
+hipError_t launch_stage_adjoint(const void* f, const void* lam, const void* lam_add, void* out,
+                                double* tau_part, int tau_blocks, double w_in, double w_add,
+                                const KParams& K, hipStream_t st);
+template <typename S>
+hipError_t launch_init_adjoint(const double* rho, const double* ux, const double* uy,
+                               const double* T, const void* lam, double* g_rho, double* g_ux,
+                               double* g_uy, double* g_T, const KParams& K, hipStream_t st);
+template <typename S>
+hipError_t launch_moments_adjoint(const void* f, const double* g_rho, const double* g_ux,
+                                  const double* g_uy, const double* g_T, void* lam,
+                                  const KParams& K, hipStream_t st);
+hipError_t launch_accumulate_scalar(const double* part, int nblocks, double scale, double* dst,
+                                    hipStream_t st);
+
+// Batched ensemble (kernels_batch.hip).
+struct GridDesc;
+template <typename S>
+hipError_t launch_batch_step(const void* fin, void* fout, const GridDesc* grids, const int4* items,
+                             int nitems, int nblocks, const KParams& shared, hipStream_t st);
+
+}  // namespace cdbm
