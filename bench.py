@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="grid side of the oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (3 times), the reference "
+                         "kernel for scaling HBM byte counters")
     return ap.parse_args()
 
 
@@ -107,6 +110,13 @@ def main():
 
     run = W.headline(seed=args.seed, n=args.n)
     out = {}
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        del a, c
 
     # mixed form: the headline number
     s = Solver.from_run(run, MIXED)

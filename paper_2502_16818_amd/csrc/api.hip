@@ -8,14 +8,18 @@
 #include <vector>
 
 #include "../../include/cdbm.h"
+#include "api_internal.hpp"
 #include "launch.hpp"
 #include "model.hpp"
 
 using cdbm::KParams;
 
-namespace {
+namespace cdbm {
 
+namespace {
 thread_local std::string g_err;
+constexpr int GRAPH_STEPS = 32;   // steps per captured graph (an even number)
+}  // namespace
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -29,58 +33,11 @@ int hip_fail(hipError_t e, const char* what) {
     return CDBM_EHIP;
 }
 
-constexpr int REDUCE_BLOCKS = 1024;
-constexpr int GRAPH_STEPS = 32;   // steps per captured graph (an even number)
-
-}  // namespace
-
-struct cdbm_handle {
-    cdbm_params p;
-    KParams k;
-    int device = 0;
-    int64_t cells = 0;
-    size_t elem = 8;
-    size_t fbytes = 0;
-    void* scratch = nullptr;    // f-sized ping-pong buffer
-    void* stage = nullptr;      // f-sized buffer for the adjoint's stage-1 state
-    void* lam_mid = nullptr;    // f-sized buffer for the adjoint's intermediate product
-    double* partials = nullptr; // reduction partials
-    int* flag = nullptr;        // device flag of the field check
-    // graph of GRAPH_STEPS steps ping-ponging between gout and scratch
-    hipGraphExec_t gexec = nullptr;
-    void* gout = nullptr;
-};
-
-namespace {
-
-bool mixed(const cdbm_handle* h) { return h->p.precision == CDBM_MIXED; }
-
-hipError_t step_once(const cdbm_handle* h, const void* fin, void* fout, hipStream_t st) {
-    return mixed(h) ? cdbm::launch_step_fused<float>(fin, fout, h->k, st)
-                    : cdbm::launch_step_fused<double>(fin, fout, h->k, st);
-}
-
 int check_device(const cdbm_handle* h) {
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (dev != h->device) return fail(CDBM_EINVAL, "handle was created on another device");
-    return CDBM_OK;
-}
-
-int check_fields(cdbm_handle* h, const double* rho, const double* ux, const double* uy,
-                 const double* T, hipStream_t st) {
-    if (!rho || !ux || !uy || !T) return fail(CDBM_EINVAL, "null field pointer");
-    hipError_t e = hipMemsetAsync(h->flag, 0, sizeof(int), st);
-    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
-    e = cdbm::launch_check_fields(rho, ux, uy, T, h->cells, h->flag, st);
-    if (e != hipSuccess) return hip_fail(e, "field check launch");
-    int bad = 0;
-    e = hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if (bad) return fail(CDBM_ENONPHYS, "rho <= 0, T <= 0 or a non-finite value in the fields");
     return CDBM_OK;
 }
 
@@ -94,45 +51,109 @@ int ensure_buffer(cdbm_handle* h, void** buf) {
     return CDBM_OK;
 }
 
-void drop_graph(cdbm_handle* h) {
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    h->gexec = nullptr;
-    h->gout = nullptr;
-}
+const char* last_error() { return g_err.c_str(); }
 
-// Capture GRAPH_STEPS steps f_out -> scratch -> f_out ... -> f_out.
-int capture_graph(cdbm_handle* h, void* fout, hipStream_t st) {
-    drop_graph(h);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    for (int s = 0; s < GRAPH_STEPS; ++s) {
-        const void* src = (s % 2 == 0) ? fout : h->scratch;
-        void* dst = (s % 2 == 0) ? h->scratch : fout;
-        hipError_t le = step_once(h, src, dst, st);
-        if (le != hipSuccess) {
-            (void)hipStreamEndCapture(st, &graph);
-            if (graph) (void)hipGraphDestroy(graph);
-            return hip_fail(le, "step launch during capture");
-        }
-    }
-    e = hipStreamEndCapture(st, &graph);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) {
-        h->gexec = nullptr;
-        return hip_fail(e, "hipGraphInstantiate");
-    }
-    h->gout = fout;
+int check_fields_range(int* flag, const double* rho, const double* ux, const double* uy,
+                       const double* T, int64_t cells, hipStream_t st) {
+    if (!rho || !ux || !uy || !T) return fail(CDBM_EINVAL, "null field pointer");
+    hipError_t e = hipMemsetAsync(flag, 0, sizeof(int), st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    e = launch_check_fields(rho, ux, uy, T, cells, flag, st);
+    if (e != hipSuccess) return hip_fail(e, "field check launch");
+    int bad = 0;
+    e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (bad) return fail(CDBM_ENONPHYS, "rho <= 0, T <= 0 or a non-finite value in the fields");
     return CDBM_OK;
 }
 
+void StepGraph::drop() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    out = nullptr;
+}
+
+int run_steps(StepFn fn, const void* ctx, const void* fin, void* fout, void* scratch, int nsteps,
+              hipStream_t st, StepGraph& graph) {
+    int remaining = nsteps;
+    hipError_t e;
+    if (nsteps % 2 == 1) {
+        e = fn(ctx, fin, fout, st);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        --remaining;
+    } else {
+        e = fn(ctx, fin, scratch, st);
+        if (e == hipSuccess) e = fn(ctx, scratch, fout, st);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        remaining -= 2;
+    }
+    // remaining is even and the state is in fout
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool can_graph = st != nullptr && hipStreamIsCapturing(st, &cs) == hipSuccess &&
+                           cs == hipStreamCaptureStatusNone;
+    if (can_graph && remaining >= GRAPH_STEPS) {
+        if (!graph.exec || graph.out != fout) {
+            graph.drop();
+            hipGraph_t g = nullptr;
+            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+            hipError_t le = hipSuccess;
+            for (int s = 0; s < GRAPH_STEPS && le == hipSuccess; ++s)
+                le = (s % 2 == 0) ? fn(ctx, fout, scratch, st) : fn(ctx, scratch, fout, st);
+            e = hipStreamEndCapture(st, &g);
+            if (le != hipSuccess || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(le != hipSuccess ? le : e, "step graph capture");
+            }
+            e = hipGraphInstantiate(&graph.exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                graph.exec = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            graph.out = fout;
+        }
+        while (remaining >= GRAPH_STEPS) {
+            e = hipGraphLaunch(graph.exec, st);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+            remaining -= GRAPH_STEPS;
+        }
+    }
+    while (remaining > 0) {
+        e = fn(ctx, fout, scratch, st);
+        if (e == hipSuccess) e = fn(ctx, scratch, fout, st);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+        remaining -= 2;
+    }
+    return CDBM_OK;
+}
+
+namespace {
+
+hipError_t step_once(const cdbm_handle* h, const void* fin, void* fout, hipStream_t st) {
+    return mixed(h) ? launch_step_fused<float>(fin, fout, h->k, h->kdev, st)
+                    : launch_step_fused<double>(fin, fout, h->k, h->kdev, st);
+}
+
+int check_fields(cdbm_handle* h, const double* rho, const double* ux, const double* uy,
+                 const double* T, hipStream_t st) {
+    return check_fields_range(h->flag, rho, ux, uy, T, h->cells, st);
+}
+
+hipError_t step_single(const void* ctx, const void* fin, void* fout, hipStream_t st) {
+    return step_once((const cdbm_handle*)ctx, fin, fout, st);
+}
+
 }  // namespace
+}  // namespace cdbm
+
+using namespace cdbm;
 
 extern "C" {
 
-const char* cdbm_last_error(void) { return g_err.c_str(); }
+const char* cdbm_last_error(void) { return cdbm::last_error(); }
 
 int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
     if (!p || !out) return fail(CDBM_EINVAL, "null argument");
@@ -154,11 +175,19 @@ int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
     h->cells = (int64_t)p->nx * p->ny;
     h->elem = mixed(h) ? sizeof(float) : sizeof(double);
     h->fbytes = (size_t)cdbm::NV * (size_t)h->cells * h->elem;
+    const int tau_blocks = ((p->nx + 63) / 64) * ((p->ny + 3) / 4);
     if (ensure_buffer(h, &h->scratch) != CDBM_OK ||
         hipMalloc(&h->partials, sizeof(double) * 4 * REDUCE_BLOCKS) != hipSuccess ||
-        hipMalloc(&h->flag, sizeof(int)) != hipSuccess) {
+        hipMalloc(&h->tau_part, sizeof(double) * tau_blocks) != hipSuccess ||
+        hipMalloc(&h->flag, sizeof(int)) != hipSuccess ||
+        hipMalloc(&h->kdev, sizeof(KParams)) != hipSuccess) {
         cdbm_destroy(h);
         return fail(CDBM_ENOMEM, "device allocation failed");
+    }
+    e = hipMemcpy(h->kdev, &h->k, sizeof(KParams), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        cdbm_destroy(h);
+        return hip_fail(e, "hipMemcpy of the run constants");
     }
     *out = h;
     return CDBM_OK;
@@ -167,12 +196,14 @@ int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
 int cdbm_destroy(cdbm_handle* h) {
     if (!h) return CDBM_OK;
     (void)hipDeviceSynchronize();
-    drop_graph(h);
+    h->graph.drop();
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->stage) (void)hipFree(h->stage);
     if (h->lam_mid) (void)hipFree(h->lam_mid);
     if (h->partials) (void)hipFree(h->partials);
+    if (h->tau_part) (void)hipFree(h->tau_part);
     if (h->flag) (void)hipFree(h->flag);
+    if (h->kdev) (void)hipFree(h->kdev);
     delete h;
     return CDBM_OK;
 }
@@ -209,43 +240,7 @@ int cdbm_step(cdbm_handle* h, const void* f_in, void* f_out, int32_t nsteps, voi
         hipError_t e = hipMemcpyAsync(f_out, f_in, h->fbytes, hipMemcpyDeviceToDevice, st);
         return e == hipSuccess ? CDBM_OK : hip_fail(e, "hipMemcpyAsync");
     }
-    // Destinations alternate between f_out and scratch and end on f_out.
-    const void* src = f_in;
-    int remaining = nsteps;
-    hipError_t e;
-    if (nsteps % 2 == 1) {
-        e = step_once(h, src, f_out, st);
-        if (e != hipSuccess) return hip_fail(e, "step launch");
-        --remaining;
-    } else {
-        e = step_once(h, src, h->scratch, st);
-        if (e != hipSuccess) return hip_fail(e, "step launch");
-        e = step_once(h, h->scratch, f_out, st);
-        if (e != hipSuccess) return hip_fail(e, "step launch");
-        remaining -= 2;
-    }
-    // remaining is even; the state is in f_out.
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    const bool can_graph = st != nullptr && hipStreamIsCapturing(st, &cs) == hipSuccess &&
-                           cs == hipStreamCaptureStatusNone;
-    if (can_graph && remaining >= GRAPH_STEPS) {
-        if (!h->gexec || h->gout != f_out) {
-            rc = capture_graph(h, f_out, st);
-            if (rc != CDBM_OK) return rc;
-        }
-        while (remaining >= GRAPH_STEPS) {
-            e = hipGraphLaunch(h->gexec, st);
-            if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-            remaining -= GRAPH_STEPS;
-        }
-    }
-    while (remaining > 0) {
-        e = step_once(h, f_out, h->scratch, st);
-        if (e == hipSuccess) e = step_once(h, h->scratch, f_out, st);
-        if (e != hipSuccess) return hip_fail(e, "step launch");
-        remaining -= 2;
-    }
-    return CDBM_OK;
+    return run_steps(step_single, h, f_in, f_out, h->scratch, nsteps, st, h->graph);
 }
 
 int cdbm_moments(cdbm_handle* h, const void* f, double* rho, double* ux, double* uy, double* T,

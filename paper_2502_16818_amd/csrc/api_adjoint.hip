@@ -1,0 +1,96 @@
+// C ABI of the reverse-mode products (include/cdbm.h).
+//
+// One step is F(f) = f/2 + E(E(f))/2 with the stage E(g) = g + dt L(g).
+// With lam' = lam^{n+1} and f1 = E(f):
+//   mu    = E'(f1)^T lam' / 2
+//   lam^n = lam' / 2 + E'(f)^T mu
+//   dL/dtau += lam' . dE/dtau(f1) / 2 + mu . dE/dtau(f)
+// f1 is recomputed from f (the unfused stage kernel) into the handle's stage
+// buffer; mu lives in a second handle-owned buffer.
+#include <hip/hip_runtime.h>
+
+#include "../../include/cdbm.h"
+#include "api_internal.hpp"
+#include "launch.hpp"
+
+using namespace cdbm;
+
+namespace cdbm {
+int stage_adjoint_blocks(const KParams& K);
+}
+
+namespace {
+
+template <typename S>
+int step_adjoint_impl(cdbm_handle* h, const void* f_n, const void* lam_np1, void* lam_n,
+                      double* dtau, hipStream_t st) {
+    const KParams& K = h->k;
+    const int nb = stage_adjoint_blocks(K);
+    hipError_t e = launch_stage<S>(f_n, nullptr, h->stage, false, K, st);
+    if (e != hipSuccess) return hip_fail(e, "stage recompute launch");
+    e = launch_stage_adjoint<S>(h->stage, lam_np1, nullptr, h->lam_mid, h->tau_part, nb, 0.5, 0.0,
+                                K, st);
+    if (e != hipSuccess) return hip_fail(e, "stage adjoint launch");
+    e = launch_accumulate_scalar(h->tau_part, nb, 1.0, dtau, st);
+    if (e != hipSuccess) return hip_fail(e, "tau accumulation launch");
+    e = launch_stage_adjoint<S>(f_n, h->lam_mid, lam_np1, lam_n, h->tau_part, nb, 1.0, 0.5, K, st);
+    if (e != hipSuccess) return hip_fail(e, "stage adjoint launch");
+    e = launch_accumulate_scalar(h->tau_part, nb, 1.0, dtau, st);
+    if (e != hipSuccess) return hip_fail(e, "tau accumulation launch");
+    return CDBM_OK;
+}
+
+bool overlaps(const void* a, const void* b, size_t n) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + n && y < x + n;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdbm_step_adjoint(cdbm_handle* h, const void* f_n, const void* lam_np1, void* lam_n,
+                      double* dL_dtau, void* stream) {
+    if (!h || !f_n || !lam_np1 || !lam_n || !dL_dtau) return fail(CDBM_EINVAL, "null argument");
+    if (overlaps(lam_n, f_n, h->fbytes) || overlaps(lam_n, lam_np1, h->fbytes))
+        return fail(CDBM_EINVAL, "lam_n overlaps f_n or lam_np1");
+    int rc = check_device(h);
+    if (rc != CDBM_OK) return rc;
+    if ((rc = ensure_buffer(h, &h->stage)) != CDBM_OK) return rc;
+    if ((rc = ensure_buffer(h, &h->lam_mid)) != CDBM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    return mixed(h) ? step_adjoint_impl<float>(h, f_n, lam_np1, lam_n, dL_dtau, st)
+                    : step_adjoint_impl<double>(h, f_n, lam_np1, lam_n, dL_dtau, st);
+}
+
+int cdbm_init_adjoint(cdbm_handle* h, const double* rho, const double* ux, const double* uy,
+                      const double* T, const void* lam_f0, double* g_rho, double* g_ux,
+                      double* g_uy, double* g_T, void* stream) {
+    if (!h || !rho || !ux || !uy || !T || !lam_f0 || !g_rho || !g_ux || !g_uy || !g_T)
+        return fail(CDBM_EINVAL, "null argument");
+    int rc = check_device(h);
+    if (rc != CDBM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e =
+        mixed(h) ? launch_init_adjoint<float>(rho, ux, uy, T, lam_f0, g_rho, g_ux, g_uy, g_T, h->k, st)
+                 : launch_init_adjoint<double>(rho, ux, uy, T, lam_f0, g_rho, g_ux, g_uy, g_T, h->k,
+                                               st);
+    return e == hipSuccess ? CDBM_OK : hip_fail(e, "init adjoint launch");
+}
+
+int cdbm_moments_adjoint(cdbm_handle* h, const void* f, const double* g_rho, const double* g_ux,
+                         const double* g_uy, const double* g_T, void* lam_f, void* stream) {
+    if (!h || !f || !g_rho || !g_ux || !g_uy || !g_T || !lam_f)
+        return fail(CDBM_EINVAL, "null argument");
+    if (overlaps(lam_f, f, h->fbytes)) return fail(CDBM_EINVAL, "lam_f overlaps f");
+    int rc = check_device(h);
+    if (rc != CDBM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = mixed(h)
+                       ? launch_moments_adjoint<float>(f, g_rho, g_ux, g_uy, g_T, lam_f, h->k, st)
+                       : launch_moments_adjoint<double>(f, g_rho, g_ux, g_uy, g_T, lam_f, h->k, st);
+    return e == hipSuccess ? CDBM_OK : hip_fail(e, "moments adjoint launch");
+}
+
+}  // extern "C"

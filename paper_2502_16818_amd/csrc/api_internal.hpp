@@ -1,0 +1,63 @@
+// Internal declarations shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/cdbm.h"
+#include "model.hpp"
+
+namespace cdbm {
+
+// Record an error message for cdbm_last_error() and return `code`.
+int fail(int code, const std::string& msg);
+// Same for a failed HIP call; returns CDBM_EHIP.
+int hip_fail(hipError_t e, const char* what);
+
+constexpr int REDUCE_BLOCKS = 1024;
+
+// A step launcher: advance one time step from `fin` to `fout` on `st`.
+using StepFn = hipError_t (*)(const void* ctx, const void* fin, void* fout, hipStream_t st);
+
+// Captured graph of an even number of steps ping-ponging out -> scratch -> out.
+struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    void* out = nullptr;
+    void drop();
+};
+
+
+}  // namespace cdbm
+
+struct cdbm_handle {
+    cdbm_params p;
+    cdbm::KParams k;
+    int device = 0;
+    int64_t cells = 0;
+    size_t elem = 8;
+    size_t fbytes = 0;
+    void* scratch = nullptr;    // f-sized ping-pong buffer
+    void* stage = nullptr;      // f-sized buffer for the adjoint's stage-1 state
+    void* lam_mid = nullptr;    // f-sized buffer for the adjoint's intermediate product
+    double* partials = nullptr; // reduction partials
+    double* tau_part = nullptr; // per-block partial sums of the adjoint's tau term
+    cdbm::KParams* kdev = nullptr;   // device copy of k
+    int* flag = nullptr;        // device flag of the field check
+    cdbm::StepGraph graph;
+};
+
+namespace cdbm {
+inline bool mixed(const cdbm_handle* h) { return h->p.precision == CDBM_MIXED; }
+int check_device(const cdbm_handle* h);
+int ensure_buffer(cdbm_handle* h, void** buf);
+int check_fields_range(int* flag, const double* rho, const double* ux, const double* uy,
+                       const double* T, int64_t cells, hipStream_t st);
+
+// Advance nsteps >= 1 from fin to fout (destinations alternate between fout
+// and scratch and end on fout; fin is never written).  Long runs replay a
+// captured graph when the stream is a non-null stream that is not itself
+// being captured.
+int run_steps(StepFn fn, const void* ctx, const void* fin, void* fout, void* scratch,
+              int nsteps, hipStream_t st, StepGraph& graph);
+}  // namespace cdbm

@@ -1,0 +1,195 @@
+// Reverse-mode kernels: transpose of one Runge-Kutta stage, of the initial
+// equilibrium and of the macroscopic moments (see adjoint.hpp).
+#include <hip/hip_runtime.h>
+
+#include "adjoint.hpp"
+#include "launch.hpp"
+
+namespace cdbm {
+
+namespace {
+
+// out = w_add * add + w_in * E'(g)^T a, and the per-block partial sums of
+// w_in * sum_i a_i dE_i/dtau = w_in * sum_i a_i dt (g_i - g_i^eq) / tau^2.
+template <typename S>
+__global__ void __launch_bounds__(256) k_stage_adjoint(const S* __restrict__ g,
+                                                       const S* __restrict__ a,
+                                                       const S* __restrict__ add,
+                                                       S* __restrict__ out, double w_in,
+                                                       double w_add, KParams K,
+                                                       double* __restrict__ tau_part) {
+    __shared__ double red[256];
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int nx = K.nx, ny = K.ny;
+    double tpart = 0.0;
+    if (x < nx && y < ny) {
+        const int64_t cells = (int64_t)nx * ny;
+        const int64_t c = (int64_t)y * nx + x;
+        double gd[NV], ad[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            gd[i] = (double)g[i * cells + c];
+            ad[i] = (double)a[i * cells + c];
+        }
+        Parity pg;
+        to_parity(gd, pg);
+        const Macro m = macro_from_parity(pg, K, K.inv_a);
+        double feq[NV];
+        equilibrium(m, K, K.a, feq);
+        const Quad q = equilibrium_vjp_q(m, K, K.a, ad);
+        const double tau2 = K.dt / (K.tau * K.tau);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const double ceq = moments_vjp_k(m, K, K.a, q, i);
+            double adv = 0.0;
+            if (SX[i] != 0) {
+                Line<S> F{g + i * cells + (int64_t)y * nx, 1, nx, K.bcx};
+                Line<S> A{a + i * cells + (int64_t)y * nx, 1, nx, K.bcx};
+                adv += K.cx[i] * (SX[i] > 0 ? nnd_transpose<S, true>(F, A, x)
+                                            : nnd_transpose<S, false>(F, A, x));
+            }
+            if (SY[i] != 0) {
+                Line<S> F{g + i * cells + x, nx, ny, K.bcy};
+                Line<S> A{a + i * cells + x, nx, ny, K.bcy};
+                adv += K.cy[i] * (SY[i] > 0 ? nnd_transpose<S, true>(F, A, y)
+                                            : nnd_transpose<S, false>(F, A, y));
+            }
+            double v = ad[i] + adv - K.z * (ad[i] - ceq);
+            v *= w_in;
+            if (w_add != 0.0) v = fma(w_add, (double)add[i * cells + c], v);
+            out[i * cells + c] = (S)v;
+            tpart = fma(ad[i], tau2 * (gd[i] - feq[i]), tpart);
+        }
+        tpart *= w_in;
+    }
+    red[threadIdx.x] = tpart;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tau_part[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+// g_q = (d f^eq(q) / d q)^T lam per cell.
+template <typename S>
+__global__ void __launch_bounds__(256) k_init_adjoint(const double* __restrict__ rho,
+                                                      const double* __restrict__ ux,
+                                                      const double* __restrict__ uy,
+                                                      const double* __restrict__ T,
+                                                      const S* __restrict__ lam,
+                                                      double* __restrict__ g_rho,
+                                                      double* __restrict__ g_ux,
+                                                      double* __restrict__ g_uy,
+                                                      double* __restrict__ g_T, KParams K,
+                                                      int64_t cells) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    double ad[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) ad[i] = (double)lam[i * cells + c];
+    const Macro m{rho[c], ux[c], uy[c], T[c]};
+    const Quad q = equilibrium_vjp_q(m, K, K.a, ad);
+    g_rho[c] = q.rho;
+    g_ux[c] = q.ux;
+    g_uy[c] = q.uy;
+    g_T[c] = q.T;
+}
+
+// lam_f = (d (rho, u, T) / d f)^T g per cell.
+template <typename S>
+__global__ void __launch_bounds__(256) k_moments_adjoint(const S* __restrict__ f,
+                                                         const double* __restrict__ g_rho,
+                                                         const double* __restrict__ g_ux,
+                                                         const double* __restrict__ g_uy,
+                                                         const double* __restrict__ g_T,
+                                                         S* __restrict__ lam, KParams K,
+                                                         int64_t cells) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    double fd[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) fd[i] = (double)f[i * cells + c];
+    Parity pg;
+    to_parity(fd, pg);
+    const Macro m = macro_from_parity(pg, K, K.inv_a);
+    const Quad q{g_rho[c], g_ux[c], g_uy[c], g_T[c]};
+#pragma unroll
+    for (int i = 0; i < NV; ++i) lam[i * cells + c] = (S)moments_vjp_k(m, K, K.a, q, i);
+}
+
+// dst[0] += scale * sum_b part[b], summed in a fixed order by one block.
+__global__ void __launch_bounds__(256) k_accumulate(const double* __restrict__ part, int n,
+                                                    double scale, double* __restrict__ dst) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < n; b += blockDim.x) s += part[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dst[0] += scale * red[0];
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+int stage_adjoint_blocks(const KParams& K) {
+    return (int)(blocks_for(K.nx, 64) * blocks_for(K.ny, 4));
+}
+
+template <typename S>
+hipError_t launch_stage_adjoint(const void* g, const void* a, const void* add, void* out,
+                                double* tau_part, int /*tau_blocks*/, double w_in, double w_add,
+                                const KParams& K, hipStream_t st) {
+    const dim3 grid(blocks_for(K.nx, 64), blocks_for(K.ny, 4));
+    hipLaunchKernelGGL(k_stage_adjoint<S>, grid, dim3(256), 0, st, (const S*)g, (const S*)a,
+                       (const S*)add, (S*)out, w_in, w_add, K, tau_part);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_init_adjoint(const double* rho, const double* ux, const double* uy,
+                               const double* T, const void* lam, double* g_rho, double* g_ux,
+                               double* g_uy, double* g_T, const KParams& K, hipStream_t st) {
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    hipLaunchKernelGGL(k_init_adjoint<S>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, rho, ux,
+                       uy, T, (const S*)lam, g_rho, g_ux, g_uy, g_T, K, cells);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_moments_adjoint(const void* f, const double* g_rho, const double* g_ux,
+                                  const double* g_uy, const double* g_T, void* lam,
+                                  const KParams& K, hipStream_t st) {
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    hipLaunchKernelGGL(k_moments_adjoint<S>, dim3(blocks_for(cells, 256)), dim3(256), 0, st,
+                       (const S*)f, g_rho, g_ux, g_uy, g_T, (S*)lam, K, cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate_scalar(const double* part, int nblocks, double scale, double* dst,
+                                    hipStream_t st) {
+    hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(256), 0, st, part, nblocks, scale, dst);
+    return hipGetLastError();
+}
+
+#define CDBM_INSTANTIATE(S)                                                                      \
+    template hipError_t launch_stage_adjoint<S>(const void*, const void*, const void*, void*,   \
+                                                double*, int, double, double, const KParams&,   \
+                                                hipStream_t);                                   \
+    template hipError_t launch_init_adjoint<S>(const double*, const double*, const double*,     \
+                                               const double*, const void*, double*, double*,    \
+                                               double*, double*, const KParams&, hipStream_t);  \
+    template hipError_t launch_moments_adjoint<S>(const void*, const double*, const double*,    \
+                                                  const double*, const double*, void*,          \
+                                                  const KParams&, hipStream_t);
+CDBM_INSTANTIATE(float)
+CDBM_INSTANTIATE(double)
+#undef CDBM_INSTANTIATE
+
+}  // namespace cdbm

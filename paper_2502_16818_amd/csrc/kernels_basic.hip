@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256) k_moments(const S* __restrict__ f, double
     load_cell(f, cells, c, fd);
     Parity g;
     to_parity(fd, g);
-    const Macro m = macro_from_parity(g, K, K.a);
+    const Macro m = macro_from_parity(g, K, K.inv_a);
     rho[c] = m.rho;
     ux[c] = m.ux;
     uy[c] = m.uy;
@@ -73,7 +73,7 @@ __global__ void __launch_bounds__(256) k_tne(const S* __restrict__ f, double* __
     load_cell(f, cells, c, fd);
     Parity g;
     to_parity(fd, g);
-    const Macro m = macro_from_parity(g, K, K.a);
+    const Macro m = macro_from_parity(g, K, K.inv_a);
     double feq[NV];
     equilibrium(m, K, K.a, feq);
     double acc[12];

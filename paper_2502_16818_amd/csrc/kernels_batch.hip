@@ -1,0 +1,77 @@
+// Batched ensemble step: one persistent launch advances every grid of the
+// batch by one time step.  The work of all grids is laid out as one sequence
+// of (grid, strip, row) triples (grid-major); block b takes the b-th of
+// gridDim.x equal contiguous pieces, so the load is balanced in strip-rows
+// however uneven the grids are.  Each grid has its own constants (sizes,
+// dt/tau, D + I, dx, dy, boundary conditions) in a device table; the
+// velocity set, and so the inverse moment matrix, is shared.
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+#include "step_fused.hpp"
+
+namespace cdbm {
+
+namespace {
+
+template <typename S>
+__global__ void __launch_bounds__(FUSED_NT) k_batch_step(const S* __restrict__ fin,
+                                                         S* __restrict__ fout,
+                                                         const KParams* __restrict__ Ks,
+                                                         const int64_t* __restrict__ f_off,
+                                                         const int64_t* __restrict__ work_start,
+                                                         int ngrids) {
+    __shared__ S F0[FUSED_SLOTS * NV * FUSED_W0];
+    __shared__ S F1[FUSED_SLOTS * NV * FUSED_W1];
+    const int64_t total = work_start[ngrids];
+    const int64_t u1 = total * (blockIdx.x + 1) / gridDim.x;
+    int64_t u = total * blockIdx.x / gridDim.x;
+    int g = 0;
+    while (u < u1) {
+        while (work_start[g + 1] <= u) ++g;   // grids are visited in order
+        const KParams& K = Ks[g];
+        const int64_t v = u - work_start[g];
+        const int s = (int)(v / K.ny);
+        const int ya = (int)(v - (int64_t)s * K.ny);
+        const int yb = (int)min((int64_t)K.ny, (int64_t)ya + (u1 - u));
+        fused_strip<S>(fin + f_off[g], fout + f_off[g], K, s * FUSED_TX, ya, yb, F0, F1);
+        u += yb - ya;
+    }
+}
+
+}  // namespace
+
+template <typename S>
+int batch_blocks() {
+    static int g = -1;
+    if (g < 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return 256;
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<S>, FUSED_NT, 0) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 1;
+        g = nb * prop.multiProcessorCount;
+    }
+    return g;
+}
+
+template <typename S>
+hipError_t launch_batch_step(const void* fin, void* fout, const KParams* Ks, const int64_t* f_off,
+                             const int64_t* work_start, int ngrids, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_step<S>, dim3(nblocks), dim3(FUSED_NT), 0, st, (const S*)fin,
+                       (S*)fout, Ks, f_off, work_start, ngrids);
+    return hipGetLastError();
+}
+
+template int batch_blocks<float>();
+template int batch_blocks<double>();
+template hipError_t launch_batch_step<float>(const void*, void*, const KParams*, const int64_t*,
+                                             const int64_t*, int, int, hipStream_t);
+template hipError_t launch_batch_step<double>(const void*, void*, const KParams*, const int64_t*,
+                                              const int64_t*, int, int, hipStream_t);
+
+}  // namespace cdbm

@@ -13,11 +13,14 @@ namespace {
 
 template <typename S>
 __global__ void __launch_bounds__(FUSED_NT) k_step_fused(const S* __restrict__ fin,
-                                                         S* __restrict__ fout, KParams K) {
+                                                         S* __restrict__ fout,
+                                                         const KParams* __restrict__ Kd) {
     __shared__ S F0[FUSED_SLOTS * NV * FUSED_W0];
     __shared__ S F1[FUSED_SLOTS * NV * FUSED_W1];
-    const GridC<S> G = grid_from<S>(K);
+    const KParams& K = *Kd;
     const int nstrips = (K.nx + FUSED_TX - 1) / FUSED_TX;
+    // Block b takes the b-th of gridDim.x equal, contiguous pieces of the
+    // strip-major sequence of (strip, row) pairs.
     const int64_t work = (int64_t)nstrips * K.ny;
     const int64_t u1 = work * (blockIdx.x + 1) / gridDim.x;
     int64_t u = work * blockIdx.x / gridDim.x;
@@ -25,7 +28,7 @@ __global__ void __launch_bounds__(FUSED_NT) k_step_fused(const S* __restrict__ f
         const int s = (int)(u / K.ny);
         const int ya = (int)(u - (int64_t)s * K.ny);
         const int yb = (int)min((int64_t)K.ny, (int64_t)ya + (u1 - u));
-        fused_strip<S>(fin, fout, K, G, s * FUSED_TX, ya, yb, F0, F1);
+        fused_strip<S>(fin, fout, K, s * FUSED_TX, ya, yb, F0, F1);
         u += yb - ya;
     }
 }
@@ -49,8 +52,8 @@ int fused_grid_blocks(const KParams& K) {
     const int nstrips = (K.nx + FUSED_TX - 1) / FUSED_TX;
     const int64_t work = (int64_t)nstrips * K.ny;
     int64_t g = (int64_t)per_cu * cus;
-    // each block should stream at least ~16 rows so the pipeline warm-up stays small
-    const int64_t cap = (work + 15) / 16;
+    // each block should stream at least ~32 rows so the pipeline warm-up stays small
+    const int64_t cap = (work + 31) / 32;
     if (g > cap) g = cap;
     return (int)(g < 1 ? 1 : g);
 }
@@ -58,13 +61,17 @@ int fused_grid_blocks(const KParams& K) {
 }  // namespace
 
 template <typename S>
-hipError_t launch_step_fused(const void* fin, void* fout, const KParams& K, hipStream_t st) {
+hipError_t launch_step_fused(const void* fin, void* fout, const KParams& K, const KParams* Kd,
+                             hipStream_t st) {
     const int g = fused_grid_blocks<S>(K);
-    hipLaunchKernelGGL(k_step_fused<S>, dim3(g), dim3(FUSED_NT), 0, st, (const S*)fin, (S*)fout, K);
+    hipLaunchKernelGGL(k_step_fused<S>, dim3(g), dim3(FUSED_NT), 0, st, (const S*)fin, (S*)fout,
+                       Kd);
     return hipGetLastError();
 }
 
-template hipError_t launch_step_fused<float>(const void*, void*, const KParams&, hipStream_t);
-template hipError_t launch_step_fused<double>(const void*, void*, const KParams&, hipStream_t);
+template hipError_t launch_step_fused<float>(const void*, void*, const KParams&, const KParams*,
+                                             hipStream_t);
+template hipError_t launch_step_fused<double>(const void*, void*, const KParams&, const KParams*,
+                                              hipStream_t);
 
 }  // namespace cdbm

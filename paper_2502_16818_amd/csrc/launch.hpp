@@ -28,9 +28,11 @@ template <typename S>
 hipError_t launch_stage(const void* fin, const void* base, void* fout, bool stage2,
                         const KParams& K, hipStream_t st);
 
-// Fused two-stage step (kernels_step.hip).
+// Fused two-stage step (kernels_step.hip).  K: host copy (launch geometry);
+// Kd: the same constants in device memory (read by the kernel).
 template <typename S>
-hipError_t launch_step_fused(const void* fin, void* fout, const KParams& K, hipStream_t st);
+hipError_t launch_step_fused(const void* fin, void* fout, const KParams& K, const KParams* Kd,
+                             hipStream_t st);
 
 // Adjoint (kernels_adjoint.hip).
 template <typename S>
@@ -48,10 +50,13 @@ hipError_t launch_moments_adjoint(const void* f, const double* g_rho, const doub
 hipError_t launch_accumulate_scalar(const double* part, int nblocks, double scale, double* dst,
                                     hipStream_t st);
 
-// Batched ensemble (kernels_batch.hip).
-struct GridDesc;
+// Batched ensemble (kernels_batch.hip).  Ks: per-grid constants (device);
+// f_off: element offset of each grid's f block (device); work_start: prefix
+// sums of the grids' strip-row counts, ngrids + 1 entries (device).
 template <typename S>
-hipError_t launch_batch_step(const void* fin, void* fout, const GridDesc* grids, const int4* items,
-                             int nitems, int nblocks, const KParams& shared, hipStream_t st);
+int batch_blocks();
+template <typename S>
+hipError_t launch_batch_step(const void* fin, void* fout, const KParams* Ks, const int64_t* f_off,
+                             const int64_t* work_start, int ngrids, int nblocks, hipStream_t st);
 
 }  // namespace cdbm

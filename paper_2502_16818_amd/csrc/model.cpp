@@ -216,6 +216,7 @@ int build_params(const cdbm_params& p, KParams& k, std::string& err) {
         k.cyf[i] = (float)k.cy[i];
     }
     k.a = 2.0 + extra_dof(p.gamma);
+    k.inv_a = 1.0 / k.a;
     k.z = p.dt / p.tau;
     k.dt = p.dt;
     k.tau = p.tau;

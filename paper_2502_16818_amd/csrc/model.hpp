@@ -50,6 +50,7 @@ struct KParams {
     double cx[NV], cy[NV];     // -dt v_ix / dx and -dt v_iy / dy
     float cxf[NV], cyf[NV];
     double a;                  // D + I
+    double inv_a;              // 1 / (D + I)
     double z;                  // dt / tau
     double dt, tau;
     int32_t nx, ny, bcx, bcy;

@@ -33,33 +33,18 @@ constexpr int FUSED_W1 = FUSED_TX + 4;     // F1 row width (= 64 = one wave)
 constexpr int FUSED_SLOTS = 2 * FUSED_R;   // ring depth
 constexpr int FUSED_NT = FUSED_R * FUSED_W1;   // 256 threads
 
-// Per-grid values the fused step needs (the velocity set and its inverse
-// moment matrix come from the shared KParams).
 template <typename S>
-struct GridC {
-    int nx, ny, bcx, bcy;
-    int64_t cells;
-    double a, z;
-    S cx[NV], cy[NV];
-};
-
+__device__ __forceinline__ S coef_x(const KParams& K, int i, int z);
+template <>
+__device__ __forceinline__ float coef_x<float>(const KParams& K, int i, int z) { return K.cxf[i + z]; }
+template <>
+__device__ __forceinline__ double coef_x<double>(const KParams& K, int i, int z) { return K.cx[i + z]; }
 template <typename S>
-__device__ __forceinline__ GridC<S> grid_from(const KParams& K) {
-    GridC<S> g;
-    g.nx = K.nx;
-    g.ny = K.ny;
-    g.bcx = K.bcx;
-    g.bcy = K.bcy;
-    g.cells = (int64_t)K.nx * K.ny;
-    g.a = K.a;
-    g.z = K.z;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        g.cx[i] = coef_x<S>(K, i);
-        g.cy[i] = coef_y<S>(K, i);
-    }
-    return g;
-}
+__device__ __forceinline__ S coef_y(const KParams& K, int i, int z);
+template <>
+__device__ __forceinline__ float coef_y<float>(const KParams& K, int i, int z) { return K.cyf[i + z]; }
+template <>
+__device__ __forceinline__ double coef_y<double>(const KParams& K, int i, int z) { return K.cy[i + z]; }
 
 // Reads of one ring buffer around one cell.  Offsets are compile-time after
 // unrolling; only one of (ox, oy) is ever nonzero.
@@ -74,11 +59,11 @@ struct RingLd {
     }
 };
 
-// Stage arithmetic with per-grid coefficients (same as stage_cell, but with
-// the grid's own dt/tau, dx, dy and D + I).
+// One stage at one cell, f + dt L(f), with every run constant read from K at
+// an opaque zero offset (see opaque_zero).
 template <typename S, class Ld>
-__device__ __forceinline__ void stage_cell_g(const Ld& ld, const KParams& K, const GridC<S>& G,
-                                             S out[NV]) {
+__device__ __forceinline__ void stage_cell_k(const Ld& ld, const KParams& K, S out[NV]) {
+    const int z = opaque_zero();
     S f[NV];
     double fd[NV];
 #pragma unroll
@@ -88,23 +73,35 @@ __device__ __forceinline__ void stage_cell_g(const Ld& ld, const KParams& K, con
     }
     Parity g;
     to_parity(fd, g);
-    const Macro m = macro_from_parity(g, K, G.a);
+    const Macro m = macro_from_parity(g, K, (&K.inv_a)[z], z);
     double feq[NV];
-    equilibrium(m, K, G.a, feq);
+    equilibrium(m, K, (&K.a)[z], feq, z);
+    const double zr = (&K.z)[z];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         S adv = S(0);
         if (SX[i] > 0)
-            adv = G.cx[i] * nnd_pos<S>(ld(i, -2, 0), ld(i, -1, 0), f[i], ld(i, 1, 0));
+            adv = coef_x<S>(K, i, z) * nnd_pos<S>(ld(i, -2, 0), ld(i, -1, 0), f[i], ld(i, 1, 0));
         else if (SX[i] < 0)
-            adv = G.cx[i] * nnd_neg<S>(ld(i, -1, 0), f[i], ld(i, 1, 0), ld(i, 2, 0));
+            adv = coef_x<S>(K, i, z) * nnd_neg<S>(ld(i, -1, 0), f[i], ld(i, 1, 0), ld(i, 2, 0));
         if (SY[i] > 0)
-            adv += G.cy[i] * nnd_pos<S>(ld(i, 0, -2), ld(i, 0, -1), f[i], ld(i, 0, 1));
+            adv += coef_y<S>(K, i, z) * nnd_pos<S>(ld(i, 0, -2), ld(i, 0, -1), f[i], ld(i, 0, 1));
         else if (SY[i] < 0)
-            adv += G.cy[i] * nnd_neg<S>(ld(i, 0, -1), f[i], ld(i, 0, 1), ld(i, 0, 2));
-        const S coll = (S)(G.z * (fd[i] - feq[i]));
+            adv += coef_y<S>(K, i, z) * nnd_neg<S>(ld(i, 0, -1), f[i], ld(i, 0, 1), ld(i, 0, 2));
+        const S coll = (S)(zr * (fd[i] - feq[i]));
         out[i] = f[i] + (adv - coll);
     }
+}
+
+// Source row of a (possibly ghost) row index: periodic wrap or edge clamp.
+// Uniform within a wave; cheap for the usual case of an offset below n.
+__device__ __forceinline__ int source_row(int r, int n, int bc) {
+    if (bc == CDBM_PERIODIC) {
+        while (r < 0) r += n;
+        while (r >= n) r -= n;
+        return r;
+    }
+    return r < 0 ? 0 : (r >= n ? n - 1 : r);
 }
 
 __device__ __forceinline__ int map_index(int i, int n, int bc) { return wrap_or_clamp(i, n, bc); }
@@ -113,16 +110,17 @@ __device__ __forceinline__ int map_index(int i, int n, int bc) { return wrap_or_
 // All threads of the block must call this together (it synchronizes).
 template <typename S>
 __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __restrict__ fout,
-                                            const KParams& K, const GridC<S>& G, int x0, int ya,
-                                            int yb, S* F0, S* F1) {
+                                            const KParams& K, int x0, int ya, int yb, S* F0,
+                                            S* F1) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;   // 0..3
-    const int nx = G.nx, ny = G.ny;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // 0..3, uniform
+    const int nx = K.nx, ny = K.ny, bcx = K.bcx, bcy = K.bcy;
+    const int64_t cells = (int64_t)nx * ny;
 
     // global columns this lane loads into F0 (lanes 0..63, plus 64..67 on lanes 0..3)
-    const int gc_a = map_index(x0 - 4 + lane, nx, G.bcx);
-    const int gc_b = map_index(x0 - 4 + 64 + (lane & 3), nx, G.bcx);
+    const int gc_a = map_index(x0 - 4 + lane, nx, bcx);
+    const int gc_b = map_index(x0 - 4 + 64 + (lane & 3), nx, bcx);
 
     // ring slot of a row: rows are >= ya - 4 - 2R when used
     const int yref0 = ya - 4 - FUSED_SLOTS;
@@ -142,8 +140,8 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
         for (int k = 0; k < LINES; ++k) {
             const int line = wave * LINES + k;       // 0..63
             const int rr = line / NV, i = line % NV;
-            const int gr = map_index(rbase + rr, ny, G.bcy);
-            const S* src = fin + (int64_t)i * G.cells + (int64_t)gr * nx;
+            const int gr = source_row(rbase + rr, ny, bcy);
+            const S* src = fin + (int64_t)i * cells + (int64_t)gr * nx;
             pre_a[k] = src[gc_a];
             pre_b[k] = (lane < 4) ? src[gc_b] : S(0);
         }
@@ -178,7 +176,7 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
                 ld.col[o + 2] = lane + 2 + o;
             }
             S out[NV];
-            stage_cell_g<S>(ld, K, G, out);
+            stage_cell_k<S>(ld, K, out);
             S* dst = F1 + slot1(r1) * NV * FUSED_W1 + lane;
 #pragma unroll
             for (int i = 0; i < NV; ++i) dst[i * FUSED_W1] = out[i];
@@ -194,19 +192,19 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
             ld.ring = F1;
 #pragma unroll
             for (int o = -2; o <= 2; ++o) {
-                const int rr = (G.bcy == CDBM_ZERO_GRADIENT) ? min(max(r2 + o, 0), ny - 1) : r2 + o;
-                const int cc = (G.bcx == CDBM_ZERO_GRADIENT) ? min(max(x + o, 0), nx - 1) : x + o;
+                const int rr = (bcy == CDBM_ZERO_GRADIENT) ? min(max(r2 + o, 0), ny - 1) : r2 + o;
+                const int cc = (bcx == CDBM_ZERO_GRADIENT) ? min(max(x + o, 0), nx - 1) : x + o;
                 ld.slot[o + 2] = slot1(rr);
                 ld.col[o + 2] = min(max(cc - (x0 - 2), 0), FUSED_W1 - 1);
             }
             S out[NV];
-            stage_cell_g<S>(ld, K, G, out);
+            stage_cell_k<S>(ld, K, out);
             if (active) {
                 const S* fn = F0 + slot0(r2) * NV * FUSED_W0 + lane + 4;
                 S* dst = fout + (int64_t)r2 * nx + x;
 #pragma unroll
                 for (int i = 0; i < NV; ++i)
-                    dst[(int64_t)i * G.cells] = S(0.5) * fn[i * FUSED_W0] + S(0.5) * out[i];
+                    dst[(int64_t)i * cells] = S(0.5) * fn[i * FUSED_W0] + S(0.5) * out[i];
             }
         }
     }

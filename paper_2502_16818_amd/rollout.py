@@ -1,0 +1,125 @@
+"""Differentiable rollout of the CDBM over the hand-written adjoint.
+
+``CDBMRollout.apply(rho0, ux0, uy0, T0, tau, solver, nsteps, every)`` runs
+f0 = f^eq(rho0, u0, T0), advances nsteps steps and returns the final
+(rho, u_x, u_y, T).  Its backward pass uses only the library's reverse-mode
+entry points: the moments adjoint seeds dL/df at the final step, every step
+is transposed with cdbm_step_adjoint (which also accumulates dL/dtau), and
+the initial-equilibrium adjoint maps dL/df0 to the initial fields.  Forward
+states are checkpointed every `every` steps; the backward pass recomputes
+the states of one segment at a time from its checkpoint.
+"""
+from __future__ import annotations
+
+import time
+from typing import Optional
+
+import torch
+
+from .cdbm import MIXED, Solver
+
+
+def _segments(nsteps: int, every: int):
+    out = []
+    k = 0
+    while k < nsteps:
+        n = min(every, nsteps - k)
+        out.append((k, n))
+        k += n
+    return out
+
+
+class CDBMRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rho0, ux0, uy0, T0, tau, solver: Solver, nsteps: int, every: int):
+        if abs(float(tau) - solver.params.tau) > 1e-15 * abs(solver.params.tau):
+            raise ValueError("tau must equal the relaxation time the solver was created with")
+        fields = [t.detach().to(torch.float64).contiguous() for t in (rho0, ux0, uy0, T0)]
+        f = solver.init(*fields)
+        buf = solver.empty_f()
+        ckpts = []
+        for _, n in _segments(nsteps, every):
+            ckpts.append(f.clone())
+            solver.step(f, buf, nsteps=n)
+            f, buf = buf, f
+        out = solver.moments(f)
+        ctx.solver = solver
+        ctx.nsteps = nsteps
+        ctx.every = every
+        ctx.ckpts = ckpts
+        ctx.f_final = f
+        ctx.save_for_backward(*fields)
+        ctx.tau_like = torch.as_tensor(tau)
+        return out
+
+    @staticmethod
+    def backward(ctx, g_rho, g_ux, g_uy, g_T):
+        s: Solver = ctx.solver
+        grads = []
+        for g in (g_rho, g_ux, g_uy, g_T):
+            grads.append(torch.zeros((s.ny, s.nx), dtype=torch.float64, device="cuda")
+                         if g is None else g.to(torch.float64).contiguous())
+        lam = s.moments_adjoint(ctx.f_final, *grads)
+        lam_next = s.empty_f()
+        dtau = torch.zeros(1, dtype=torch.float64, device="cuda")
+        segs = _segments(ctx.nsteps, ctx.every)
+        states = [s.empty_f() for _ in range(min(ctx.every, ctx.nsteps))]
+        for (k0, n), ck in zip(reversed(segs), reversed(ctx.ckpts)):
+            states[0].copy_(ck)
+            for j in range(1, n):
+                s.step(states[j - 1], states[j], nsteps=1)
+            for j in reversed(range(n)):
+                s.step_adjoint(states[j], lam, lam_next, dtau)
+                lam, lam_next = lam_next, lam
+        rho0, ux0, uy0, T0 = ctx.saved_tensors
+        g0 = s.init_adjoint(rho0, ux0, uy0, T0, lam)
+        gtau = dtau.reshape(()).to(ctx.tau_like.dtype).to(ctx.tau_like.device) \
+            if ctx.needs_input_grad[4] else None
+        return (*g0, gtau, None, None, None)
+
+
+def rollout(solver: Solver, rho0, ux0, uy0, T0, tau, nsteps: int, every: int = 100):
+    return CDBMRollout.apply(rho0, ux0, uy0, T0, tau, solver, nsteps, every)
+
+
+def adjoint_forward_ratio(n: int = 256, steps: int = 2000, every: int = 100,
+                          precision: int = MIXED, seed: int = 0) -> dict:
+    """Wall-time ratio of the backward to the forward pass of the gradient
+    workload: n x n periodic grid, smooth random fields, L2 mismatch of the
+    final density against a target run from perturbed fields with 1.1 tau."""
+    import workloads as W
+
+    base, tgt = W.adjoint_problem(n=n, seed=seed, steps=steps)
+    s_t = Solver.from_run(tgt, precision)
+    ft = s_t.init(tgt.rho, tgt.ux, tgt.uy, tgt.T)
+    ft = s_t.step(ft, nsteps=steps)
+    rho_t = s_t.moments(ft)[0].clone()
+    s_t.close()
+    del ft
+
+    s = Solver.from_run(base, precision)
+    dev = torch.device("cuda")
+    fields = [torch.tensor(a, dtype=torch.float64, device=dev, requires_grad=True)
+              for a in (base.rho, base.ux, base.uy, base.T)]
+    tau = torch.tensor(base.tau, dtype=torch.float64, device=dev, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rho, ux, uy, T = rollout(s, *fields, tau, steps, every)
+    loss = ((rho - rho_t) ** 2).mean()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = {
+        "workload": f"{n}x{n} periodic, {steps} steps, checkpoint every {every}",
+        "precision": "mixed" if precision == MIXED else "fp64",
+        "forward_ms_per_step": (t1 - t0) * 1e3 / steps,
+        "backward_ms_per_step": (t2 - t1) * 1e3 / steps,
+        "ratio": (t2 - t1) / (t1 - t0),
+        "loss": float(loss),
+        "grad_tau": float(tau.grad),
+        "grad_norms": [float(f.grad.norm()) for f in fields],
+    }
+    s.close()
+    return out

@@ -1,0 +1,211 @@
+"""Parity of the hand-written reverse-mode path with the oracle's reverse-mode
+derivative, and of the differentiable rollout with finite differences."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cdbm as C
+import workloads as W
+from helpers import oracle_f0, rel_l2, rel_max, to_np
+
+pytestmark = pytest.mark.gpu
+
+FP64, MIXED = 0, 1
+
+
+def _solver(run, precision):
+    from paper_2502_16818_amd import Solver
+    print(f"[case] {run.name} {run.nx}x{run.ny} bc=({run.bc_x},{run.bc_y}) precision={precision}",
+          flush=True)
+    return Solver.from_run(run, precision)
+
+
+def _cases():
+    a = W.random_periodic(37, 23, seed=1, dt=1e-4, tau=2e-4)
+    b = W.random_periodic(21, 13, seed=2, dt=1e-4, tau=1e-4)
+    b.bc_x = W.ZERO_GRADIENT
+    b.bc_y = W.ZERO_GRADIENT
+    c = W.random_periodic(40, 1, seed=3, dt=1e-4, tau=1e-4)
+    c.bc_x = W.ZERO_GRADIENT
+    d = W.random_periodic(3, 2, seed=4, dt=1e-4, tau=1e-4)
+    e = W.random_periodic(64, 9, seed=5, dt=1e-4, tau=1e-4, vset="tg")
+    e.bc_y = W.ZERO_GRADIENT
+    return [a, b, c, d, e]
+
+
+def _state(run, nsteps=2):
+    """A generic (non-equilibrium) state: the oracle after a couple of steps."""
+    p, f0 = oracle_f0(run)
+    return p, C.run(f0, p, nsteps)
+
+
+def _cuda(t, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(t.numpy() if isinstance(t, torch.Tensor) else t)) \
+        .to(dtype).cuda()
+
+
+@pytest.mark.parametrize("run", _cases(), ids=lambda r: f"{r.name}_bc{r.bc_x}{r.bc_y}")
+def test_step_adjoint_fp64_matches_oracle(run):
+    p, f = _state(run)
+    lam = torch.from_numpy(np.random.default_rng(7).standard_normal(f.shape))
+    want_l, want_tau = C.step_vjp(f, lam, p)
+    s = _solver(run, FP64)
+    got_l, dtau = s.step_adjoint(_cuda(f), _cuda(lam))
+    err = rel_max(to_np(got_l), want_l.numpy())
+    terr = abs(float(dtau.item()) - want_tau) / abs(want_tau)
+    print(f"  lam rel err {err:.2e}, dtau rel err {terr:.2e}")
+    assert err < 1e-11
+    assert terr < 1e-10
+
+
+def test_step_adjoint_accumulates_tau():
+    run = _cases()[0]
+    p, f = _state(run)
+    lam = torch.from_numpy(np.random.default_rng(8).standard_normal(f.shape))
+    s = _solver(run, FP64)
+    dtau = torch.full((1,), 5.0, dtype=torch.float64, device="cuda")
+    _, dtau = s.step_adjoint(_cuda(f), _cuda(lam), dtau=dtau)
+    _, want = C.step_vjp(f, lam, p)
+    assert abs(dtau.item() - 5.0 - want) <= 1e-10 * abs(want)
+
+
+@pytest.mark.parametrize("run", _cases()[:3], ids=lambda r: r.name)
+def test_init_and_moments_adjoint_fp64(run):
+    p, f = _state(run)
+    rng = np.random.default_rng(9)
+    lam = torch.from_numpy(rng.standard_normal(f.shape))
+    s = _solver(run, FP64)
+    fields = [torch.from_numpy(a.copy()) for a in (run.rho, run.ux, run.uy, run.T)]
+    want = C.init_vjp(*fields, lam, p)
+    got = s.init_adjoint(run.rho, run.ux, run.uy, run.T, _cuda(lam))
+    for g, w in zip(got, want):
+        assert rel_max(to_np(g), w.numpy()) < 1e-11
+    gs = [rng.standard_normal(run.rho.shape) for _ in range(4)]
+    want_f = C.moments_vjp(f, *gs, p)
+    got_f = s.moments_adjoint(_cuda(f), *gs)
+    assert rel_max(to_np(got_f), want_f.numpy()) < 1e-11
+
+
+@pytest.mark.parametrize("run", _cases()[:3], ids=lambda r: r.name)
+def test_step_adjoint_mixed_against_fp64_oracle(run):
+    """The mixed form stores f and lambda in FP32; the oracle gets the same
+    FP32-rounded inputs and differentiates in FP64, so the comparison sees
+    only the FP32 arithmetic of the NND part."""
+    p, f = _state(run)
+    lam = torch.from_numpy(np.random.default_rng(10).standard_normal(f.shape))
+    f = f.float().double()
+    lam = lam.float().double()
+    want_l, want_tau = C.step_vjp(f, lam, p)
+    s = _solver(run, MIXED)
+    got_l, dtau = s.step_adjoint(_cuda(f, torch.float32), _cuda(lam, torch.float32))
+    err = rel_l2(to_np(got_l), want_l.numpy())
+    # The tau term is sum_i lam_i dt (g_i - g_i^eq) / tau^2 over both stages;
+    # the recomputed stage state g = f^(1) is held in FP32 like the forward's,
+    # so it carries an error of a few FP32 ulps of |f^(1)|, which the
+    # difference g - g^eq does not shrink.
+    f1 = f + p.dt * C.rhs(f, p)
+    bound = 8 * 2.0 ** -24 * p.dt / p.tau ** 2 * float((lam.abs() * f1.abs()).sum())
+    tdiff = abs(float(dtau.item()) - want_tau)
+    print(f"  mixed lam rel L2 {err:.2e}, dtau err {tdiff:.3e} (bound {bound:.3e}, "
+          f"rel {tdiff / abs(want_tau):.2e})")
+    assert err < 1e-5
+    assert tdiff <= bound
+
+
+def test_rollout_gradients_fp64_match_oracle_chain():
+    """Gradients of a final-density loss through 12 steps (checkpoint every 5)
+    against reverse-mode differentiation of the oracle's 12-step map."""
+    from paper_2502_16818_amd.rollout import rollout
+    run = W.random_periodic(24, 16, seed=11, dt=1e-4, tau=2e-4)
+    nsteps = 12
+    p = C.Params.from_run(run)
+    target = torch.from_numpy(np.random.default_rng(12).uniform(0.9, 1.1, (run.ny, run.nx)))
+    # oracle: autograd through the oracle definition
+    ins = [torch.from_numpy(a.copy()).requires_grad_(True) for a in (run.rho, run.ux, run.uy, run.T)]
+    tau_o = torch.tensor(run.tau, dtype=C.DT, requires_grad=True)
+    fo = C.initial_distribution(*ins, p)
+    fo = C.run(fo, p, nsteps, tau_o)
+    rho_o = C.fields(fo, p)[0]
+    loss_o = ((rho_o - target) ** 2).mean()
+    loss_o.backward()
+    # GPU
+    s = _solver(run, FP64)
+    g_in = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True)
+            for a in (run.rho, run.ux, run.uy, run.T)]
+    tau = torch.tensor(run.tau, dtype=torch.float64, device="cuda", requires_grad=True)
+    rho, ux, uy, T = rollout(s, *g_in, tau, nsteps, 5)
+    loss = ((rho - target.cuda()) ** 2).mean()
+    loss.backward()
+    assert abs(loss.item() - loss_o.item()) <= 1e-12 * abs(loss_o.item())
+    for g, o in zip(g_in, ins):
+        assert rel_max(to_np(g.grad), o.grad.numpy()) < 1e-9
+    assert abs(tau.grad.item() - tau_o.grad.item()) <= 1e-9 * abs(tau_o.grad.item())
+
+
+def test_rollout_directional_derivative_matches_finite_difference():
+    """At a larger size, where the oracle is too slow: <grad L, d> against a
+    central difference of the GPU's own FP64 forward map."""
+    from paper_2502_16818_amd import Solver
+    from paper_2502_16818_amd.rollout import rollout
+    run = W.random_periodic(64, 64, seed=13, dt=2e-5, tau=1e-4)
+    nsteps = 150
+    rng = np.random.default_rng(14)
+    target = torch.tensor(rng.uniform(0.9, 1.1, (run.ny, run.nx)), device="cuda")
+    s = _solver(run, FP64)
+
+    def loss_of(fields, tau_val=None):
+        sol = s if tau_val is None else Solver.from_run(run.with_fields(*run_fields(fields), tau=tau_val), FP64)
+        f = sol.init(*fields)
+        f = sol.step(f, nsteps=nsteps)
+        rho = sol.moments(f)[0]
+        return ((rho - target) ** 2).mean().item()
+
+    def run_fields(fields):
+        return [f.cpu().numpy() for f in fields]
+
+    base = [torch.tensor(a, dtype=torch.float64, device="cuda") for a in (run.rho, run.ux, run.uy, run.T)]
+    g_in = [b.clone().requires_grad_(True) for b in base]
+    tau = torch.tensor(run.tau, dtype=torch.float64, device="cuda", requires_grad=True)
+    rho, _, _, _ = rollout(s, *g_in, tau, nsteps, 50)
+    ((rho - target) ** 2).mean().backward()
+    dirs = [torch.tensor(W.fourier_field(rng, run.nx, run.ny), device="cuda") * sc
+            for sc in (0.01, 0.003, 0.003, 0.01)]
+    ad = sum(float((g.grad * d).sum()) for g, d in zip(g_in, dirs))
+    # The map is piecewise smooth (minmod switches) and its FP64 evaluation
+    # carries ~1e-14 relative noise after 150 steps: h = 1e-5 balances the two.
+    h = 1e-5
+    lp = loss_of([b + h * d for b, d in zip(base, dirs)])
+    lm = loss_of([b - h * d for b, d in zip(base, dirs)])
+    fd = (lp - lm) / (2 * h)
+    print(f"  directional derivative: adjoint {ad:.6e} fd {fd:.6e}")
+    assert abs(ad - fd) <= 5e-5 * abs(fd)
+    ht = run.tau * 1e-5
+    lpt = loss_of(base, run.tau + ht)
+    lmt = loss_of(base, run.tau - ht)
+    fdt = (lpt - lmt) / (2 * ht)
+    print(f"  tau derivative: adjoint {tau.grad.item():.6e} fd {fdt:.6e}")
+    assert abs(tau.grad.item() - fdt) <= 5e-5 * abs(fdt)
+
+
+def test_rollout_tau_gradient_matches_oracle_autograd_32x32():
+    """dL/dtau over 20 steps of a 32 x 32 grid against reverse-mode
+    differentiation of the oracle (the finite difference above is only good
+    to ~1e-6 because of FP64 noise and minmod switches)."""
+    from paper_2502_16818_amd.rollout import rollout
+    run = W.random_periodic(32, 32, seed=13, dt=2e-5, tau=1e-4)
+    nsteps = 20
+    target = torch.from_numpy(np.random.default_rng(14).uniform(0.9, 1.1, (run.ny, run.nx)))
+    p = C.Params.from_run(run)
+    ins = [torch.from_numpy(a.copy()).requires_grad_(True) for a in (run.rho, run.ux, run.uy, run.T)]
+    tau_o = torch.tensor(run.tau, dtype=C.DT, requires_grad=True)
+    fo = C.run(C.initial_distribution(*ins, p), p, nsteps, tau_o)
+    ((C.fields(fo, p)[0] - target) ** 2).mean().backward()
+    s = _solver(run, FP64)
+    g_in = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True)
+            for a in (run.rho, run.ux, run.uy, run.T)]
+    tau = torch.tensor(run.tau, dtype=torch.float64, device="cuda", requires_grad=True)
+    rho, _, _, _ = rollout(s, *g_in, tau, nsteps, 7)
+    ((rho - target.cuda()) ** 2).mean().backward()
+    assert abs(tau.grad.item() - tau_o.grad.item()) <= 1e-8 * abs(tau_o.grad.item())
+    for g, o in zip(g_in, ins):
+        assert rel_max(to_np(g.grad), o.grad.numpy()) < 1e-8

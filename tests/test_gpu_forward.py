@@ -26,7 +26,7 @@ def _cases():
     lax = W.lax_tube(nx=150, dx=2e-3)
     rnd = W.random_periodic(137, 23, seed=1, dt=1e-4, tau=2e-4)     # 3 strips, ragged tail
     tg = W.taylor_green_paper(n=40)
-    acl = W.lax_acoustic_2d(130, ny=19, seed=2, length=2 * 130 / 4096)
+    acl = W.lax_acoustic_2d(130, ny=19, seed=2)
     zg = W.random_periodic(61, 9, seed=5, dt=1e-4, tau=1e-4)
     zg.bc_x = W.ZERO_GRADIENT
     zg.bc_y = W.ZERO_GRADIENT
