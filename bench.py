@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--n", type=int, default=4096, help="grid side of the headline workload")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="grid side of the oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=6)
@@ -92,6 +94,29 @@ def cpu_baseline(run_full, side, steps):
             "sample": f"{side}x{side} cells of the headline setup (same dx, dt, tau, gamma, "
                       f"velocity set), {steps} FP64 steps after one warm-up step, "
                       f"{el:.1f} s"}
+
+
+def batched_ensemble(steps, warmup):
+    """The 96-grid ensemble (sizes 128..1024, own gamma and tau per grid) in
+    the mixed form, one persistent launch per step."""
+    import torch
+    import workloads as W
+    from paper_2502_16818_amd import MIXED, Batch, make_params
+    runs = W.batched_ensemble()
+    ps = [make_params(r.nx, r.ny, r.dx, r.dy, r.dt, r.tau, r.gamma, r.v, r.eta, r.bc_x, r.bc_y,
+                      MIXED) for r in runs]
+    b = Batch(ps)
+    fa = b.init([(r.rho, r.ux, r.uy, r.T) for r in runs])
+    fb = b.empty_f()
+    t, _ = time_steps(b, fa, fb, steps, warmup)
+    cells = sum(r.cells for r in runs)
+    ach = 2 * 4 * 16 * cells / t / 1e9
+    res = {"grids": len(runs), "cells": cells, "steps": steps, "ms_per_step": t * 1e3,
+           "value": 16 * cells / t, "unit": "cell-velocity updates/s",
+           "roofline_frac": ach / HBM_PEAK_GBS, "achieved_GBs": ach}
+    del fa, fb
+    b.close()
+    return res
 
 
 def run_full_seed(run):
@@ -169,12 +194,12 @@ def main():
         del fa, fb
         s.close()
 
+    if not args.no_batch:
+        out["batched"] = batched_ensemble(args.batch_steps, args.warmup)
+
     if not args.no_adjoint:
-        try:
-            from paper_2502_16818_amd.rollout import adjoint_forward_ratio
-            out["adjoint"] = adjoint_forward_ratio()
-        except ImportError:
-            out["adjoint"] = None
+        from paper_2502_16818_amd.rollout import adjoint_forward_ratio
+        out["adjoint"] = adjoint_forward_ratio()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(run, args.cpu_sample, args.cpu_steps)

@@ -135,8 +135,10 @@ int cdbm_conserved_totals(cdbm_handle* h, const void* f, double* out4, void* str
 
 /* Reverse-mode product of one time step F (the map of cdbm_step with
  * nsteps = 1): lam_n = (dF/df)^T(f_n) lam_np1 and *dL_dtau += (dF/dtau)^T lam_np1.
- * f_n, lam_np1, lam_n: device [16][ny][nx] in the handle's precision;
- * lam_n must not overlap f_n or lam_np1.  dL_dtau: device double[1],
+ * f_n: device [16][ny][nx] in the handle's precision.  lam_np1, lam_n:
+ * device double [16][ny][nx] in both precision forms (adjoint vectors carry
+ * gradients in small deviations between velocities that FP32 would round
+ * away); lam_n must not overlap f_n or lam_np1.  dL_dtau: device double[1],
  * accumulated (never overwritten).  minmod passes the derivative to its first
  * argument on a tie |X| = |Y| and none when its value is 0 (the branch order
  * of Eq. (16)).  Uses the handle's scratch buffer, so calls on one handle
@@ -146,13 +148,14 @@ int cdbm_step_adjoint(cdbm_handle* h, const void* f_n, const void* lam_np1, void
 
 /* Reverse-mode product of cdbm_init: g_q = (d f^eq(q) / d q)^T lam_f0 for
  * q = (rho, u_x, u_y, T) taken from the given fields (device double [ny][nx]).
- * lam_f0: device [16][ny][nx] in the handle's precision.  Outputs overwritten. */
+ * lam_f0: device double [16][ny][nx].  Outputs overwritten. */
 int cdbm_init_adjoint(cdbm_handle* h, const double* rho, const double* ux, const double* uy,
                       const double* T, const void* lam_f0, double* g_rho, double* g_ux,
                       double* g_uy, double* g_T, void* stream);
 
 /* Reverse-mode product of cdbm_moments: lam_f = (d(rho, u, T)/df)^T g.
- * g_*: device double [ny][nx]; lam_f: device [16][ny][nx], overwritten. */
+ * f: device [16][ny][nx] in the handle's precision; g_*: device double
+ * [ny][nx]; lam_f: device double [16][ny][nx], overwritten. */
 int cdbm_moments_adjoint(cdbm_handle* h, const void* f, const double* g_rho,
                          const double* g_ux, const double* g_uy, const double* g_T,
                          void* lam_f, void* stream);

@@ -192,17 +192,24 @@ class Solver:
                "cdbm_conserved_totals")
         return out
 
-    # -- reverse mode --------------------------------------------------------
+    # -- reverse mode (adjoint vectors are float64 in both forms) -------------
+    def empty_lam(self) -> torch.Tensor:
+        return torch.empty((16, self.ny, self.nx), dtype=torch.float64, device="cuda")
+
     def step_adjoint(self, f_n: torch.Tensor, lam_np1: torch.Tensor,
                      lam_n: Optional[torch.Tensor] = None,
                      dtau: Optional[torch.Tensor] = None):
-        lam_n = self.empty_f() if lam_n is None else lam_n
+        if lam_np1.dtype != torch.float64:
+            raise ValueError("adjoint vectors are float64")
+        lam_n = self.empty_lam() if lam_n is None else lam_n
         dtau = torch.zeros(1, dtype=torch.float64, device="cuda") if dtau is None else dtau
         _check(load().cdbm_step_adjoint(self._h, _ptr(f_n), _ptr(lam_np1), _ptr(lam_n), _ptr(dtau),
                                         _stream()), "cdbm_step_adjoint")
         return lam_n, dtau
 
     def init_adjoint(self, rho, ux, uy, T, lam_f0: torch.Tensor):
+        if lam_f0.dtype != torch.float64:
+            raise ValueError("adjoint vectors are float64")
         fs = [self._field(a) for a in (rho, ux, uy, T)]
         outs = [self.empty_field() for _ in range(4)]
         _check(load().cdbm_init_adjoint(self._h, *[_ptr(a) for a in fs], _ptr(lam_f0),
@@ -212,7 +219,7 @@ class Solver:
     def moments_adjoint(self, f: torch.Tensor, g_rho, g_ux, g_uy, g_T,
                         out: Optional[torch.Tensor] = None) -> torch.Tensor:
         gs = [self._field(g) for g in (g_rho, g_ux, g_uy, g_T)]
-        out = self.empty_f() if out is None else out
+        out = self.empty_lam() if out is None else out
         _check(load().cdbm_moments_adjoint(self._h, _ptr(f), *[_ptr(g) for g in gs], _ptr(out),
                                            _stream()), "cdbm_moments_adjoint")
         return out

@@ -151,8 +151,9 @@ __device__ __forceinline__ void face_sel(const Line<S>& F, int x, double& al, do
 }
 
 // Gather of the NND transpose at extended position p (see the header).
+// F: the state (selections are taken in its own precision); A: the adjoint.
 template <typename S, bool POS>
-__device__ __forceinline__ double nnd_gather(const Line<S>& F, const Line<S>& A, int p) {
+__device__ __forceinline__ double nnd_gather(const Line<S>& F, const Line<double>& A, int p) {
     double acc = 0.0;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
@@ -181,14 +182,14 @@ __device__ __forceinline__ double nnd_gather(const Line<S>& F, const Line<S>& A,
             else if (k == 0) coef = -1.0 + 0.5 * (b2 - a1 + b1);
             else coef = -0.5 * b1;
         }
-        acc = fma(coef, (double)A.at(x), acc);
+        acc = fma(coef, A.at(x), acc);
     }
     return acc;
 }
 
 // Full NND transpose at real cell y (ghost aliases folded in).
 template <typename S, bool POS>
-__device__ __forceinline__ double nnd_transpose(const Line<S>& F, const Line<S>& A, int y) {
+__device__ __forceinline__ double nnd_transpose(const Line<S>& F, const Line<double>& A, int y) {
     double acc = nnd_gather<S, POS>(F, A, y);
     if (F.bc == CDBM_ZERO_GRADIENT) {
         if (y == 0) acc += nnd_gather<S, POS>(F, A, -1) + nnd_gather<S, POS>(F, A, -2);

@@ -6,7 +6,10 @@
 //   lam^n = lam' / 2 + E'(f)^T mu
 //   dL/dtau += lam' . dE/dtau(f1) / 2 + mu . dE/dtau(f)
 // f1 is recomputed from f (the unfused stage kernel) into the handle's stage
-// buffer; mu lives in a second handle-owned buffer.
+// buffer; mu lives in a second handle-owned buffer.  Adjoint vectors are
+// double in both precision forms: for a loss of the density alone lam_i is
+// close to one value for all i, and the gradient with respect to u and T is
+// carried by its small deviations, which FP32 storage would round away.
 #include <hip/hip_runtime.h>
 
 #include "../../include/cdbm.h"
@@ -40,10 +43,11 @@ int step_adjoint_impl(cdbm_handle* h, const void* f_n, const void* lam_np1, void
     return CDBM_OK;
 }
 
-bool overlaps(const void* a, const void* b, size_t n) {
+// Do [a, a + an) and [b, b + bn) intersect?
+bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
     const char* x = (const char*)a;
     const char* y = (const char*)b;
-    return x < y + n && y < x + n;
+    return x < y + bn && y < x + an;
 }
 
 }  // namespace
@@ -53,12 +57,17 @@ extern "C" {
 int cdbm_step_adjoint(cdbm_handle* h, const void* f_n, const void* lam_np1, void* lam_n,
                       double* dL_dtau, void* stream) {
     if (!h || !f_n || !lam_np1 || !lam_n || !dL_dtau) return fail(CDBM_EINVAL, "null argument");
-    if (overlaps(lam_n, f_n, h->fbytes) || overlaps(lam_n, lam_np1, h->fbytes))
+    const size_t lbytes = sizeof(double) * (size_t)NV * (size_t)h->cells;
+    if (overlaps(lam_n, lbytes, f_n, h->fbytes) || overlaps(lam_n, lbytes, lam_np1, lbytes))
         return fail(CDBM_EINVAL, "lam_n overlaps f_n or lam_np1");
     int rc = check_device(h);
     if (rc != CDBM_OK) return rc;
     if ((rc = ensure_buffer(h, &h->stage)) != CDBM_OK) return rc;
-    if ((rc = ensure_buffer(h, &h->lam_mid)) != CDBM_OK) return rc;
+    if (!h->lam_mid &&
+        hipMalloc(&h->lam_mid, sizeof(double) * (size_t)NV * (size_t)h->cells) != hipSuccess) {
+        h->lam_mid = nullptr;
+        return fail(CDBM_ENOMEM, "hipMalloc of the adjoint buffer failed");
+    }
     hipStream_t st = (hipStream_t)stream;
     return mixed(h) ? step_adjoint_impl<float>(h, f_n, lam_np1, lam_n, dL_dtau, st)
                     : step_adjoint_impl<double>(h, f_n, lam_np1, lam_n, dL_dtau, st);
@@ -83,7 +92,8 @@ int cdbm_moments_adjoint(cdbm_handle* h, const void* f, const double* g_rho, con
                          const double* g_uy, const double* g_T, void* lam_f, void* stream) {
     if (!h || !f || !g_rho || !g_ux || !g_uy || !g_T || !lam_f)
         return fail(CDBM_EINVAL, "null argument");
-    if (overlaps(lam_f, f, h->fbytes)) return fail(CDBM_EINVAL, "lam_f overlaps f");
+    if (overlaps(lam_f, sizeof(double) * (size_t)NV * (size_t)h->cells, f, h->fbytes))
+        return fail(CDBM_EINVAL, "lam_f overlaps f");
     int rc = check_device(h);
     if (rc != CDBM_OK) return rc;
     hipStream_t st = (hipStream_t)stream;

@@ -11,11 +11,12 @@ namespace {
 
 // out = w_add * add + w_in * E'(g)^T a, and the per-block partial sums of
 // w_in * sum_i a_i dE_i/dtau = w_in * sum_i a_i dt (g_i - g_i^eq) / tau^2.
+// The state g is in the storage precision S; adjoint vectors are double.
 template <typename S>
 __global__ void __launch_bounds__(256) k_stage_adjoint(const S* __restrict__ g,
-                                                       const S* __restrict__ a,
-                                                       const S* __restrict__ add,
-                                                       S* __restrict__ out, double w_in,
+                                                       const double* __restrict__ a,
+                                                       const double* __restrict__ add,
+                                                       double* __restrict__ out, double w_in,
                                                        double w_add, KParams K,
                                                        double* __restrict__ tau_part) {
     __shared__ double red[256];
@@ -30,7 +31,7 @@ __global__ void __launch_bounds__(256) k_stage_adjoint(const S* __restrict__ g,
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             gd[i] = (double)g[i * cells + c];
-            ad[i] = (double)a[i * cells + c];
+            ad[i] = a[i * cells + c];
         }
         Parity pg;
         to_parity(gd, pg);
@@ -45,20 +46,20 @@ __global__ void __launch_bounds__(256) k_stage_adjoint(const S* __restrict__ g,
             double adv = 0.0;
             if (SX[i] != 0) {
                 Line<S> F{g + i * cells + (int64_t)y * nx, 1, nx, K.bcx};
-                Line<S> A{a + i * cells + (int64_t)y * nx, 1, nx, K.bcx};
+                Line<double> A{a + i * cells + (int64_t)y * nx, 1, nx, K.bcx};
                 adv += K.cx[i] * (SX[i] > 0 ? nnd_transpose<S, true>(F, A, x)
                                             : nnd_transpose<S, false>(F, A, x));
             }
             if (SY[i] != 0) {
                 Line<S> F{g + i * cells + x, nx, ny, K.bcy};
-                Line<S> A{a + i * cells + x, nx, ny, K.bcy};
+                Line<double> A{a + i * cells + x, nx, ny, K.bcy};
                 adv += K.cy[i] * (SY[i] > 0 ? nnd_transpose<S, true>(F, A, y)
                                             : nnd_transpose<S, false>(F, A, y));
             }
             double v = ad[i] + adv - K.z * (ad[i] - ceq);
             v *= w_in;
-            if (w_add != 0.0) v = fma(w_add, (double)add[i * cells + c], v);
-            out[i * cells + c] = (S)v;
+            if (w_add != 0.0) v = fma(w_add, add[i * cells + c], v);
+            out[i * cells + c] = v;
             tpart = fma(ad[i], tau2 * (gd[i] - feq[i]), tpart);
         }
         tpart *= w_in;
@@ -78,7 +79,7 @@ __global__ void __launch_bounds__(256) k_init_adjoint(const double* __restrict__
                                                       const double* __restrict__ ux,
                                                       const double* __restrict__ uy,
                                                       const double* __restrict__ T,
-                                                      const S* __restrict__ lam,
+                                                      const double* __restrict__ lam,
                                                       double* __restrict__ g_rho,
                                                       double* __restrict__ g_ux,
                                                       double* __restrict__ g_uy,
@@ -88,7 +89,7 @@ __global__ void __launch_bounds__(256) k_init_adjoint(const double* __restrict__
     if (c >= cells) return;
     double ad[NV];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) ad[i] = (double)lam[i * cells + c];
+    for (int i = 0; i < NV; ++i) ad[i] = lam[i * cells + c];
     const Macro m{rho[c], ux[c], uy[c], T[c]};
     const Quad q = equilibrium_vjp_q(m, K, K.a, ad);
     g_rho[c] = q.rho;
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(256) k_moments_adjoint(const S* __restrict__ f
                                                          const double* __restrict__ g_ux,
                                                          const double* __restrict__ g_uy,
                                                          const double* __restrict__ g_T,
-                                                         S* __restrict__ lam, KParams K,
+                                                         double* __restrict__ lam, KParams K,
                                                          int64_t cells) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(256) k_moments_adjoint(const S* __restrict__ f
     const Macro m = macro_from_parity(pg, K, K.inv_a);
     const Quad q{g_rho[c], g_ux[c], g_uy[c], g_T[c]};
 #pragma unroll
-    for (int i = 0; i < NV; ++i) lam[i * cells + c] = (S)moments_vjp_k(m, K, K.a, q, i);
+    for (int i = 0; i < NV; ++i) lam[i * cells + c] = moments_vjp_k(m, K, K.a, q, i);
 }
 
 // dst[0] += scale * sum_b part[b], summed in a fixed order by one block.
@@ -147,8 +148,8 @@ hipError_t launch_stage_adjoint(const void* g, const void* a, const void* add, v
                                 double* tau_part, int /*tau_blocks*/, double w_in, double w_add,
                                 const KParams& K, hipStream_t st) {
     const dim3 grid(blocks_for(K.nx, 64), blocks_for(K.ny, 4));
-    hipLaunchKernelGGL(k_stage_adjoint<S>, grid, dim3(256), 0, st, (const S*)g, (const S*)a,
-                       (const S*)add, (S*)out, w_in, w_add, K, tau_part);
+    hipLaunchKernelGGL(k_stage_adjoint<S>, grid, dim3(256), 0, st, (const S*)g, (const double*)a,
+                       (const double*)add, (double*)out, w_in, w_add, K, tau_part);
     return hipGetLastError();
 }
 
@@ -158,7 +159,7 @@ hipError_t launch_init_adjoint(const double* rho, const double* ux, const double
                                double* g_uy, double* g_T, const KParams& K, hipStream_t st) {
     const int64_t cells = (int64_t)K.nx * K.ny;
     hipLaunchKernelGGL(k_init_adjoint<S>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, rho, ux,
-                       uy, T, (const S*)lam, g_rho, g_ux, g_uy, g_T, K, cells);
+                       uy, T, (const double*)lam, g_rho, g_ux, g_uy, g_T, K, cells);
     return hipGetLastError();
 }
 
@@ -168,7 +169,7 @@ hipError_t launch_moments_adjoint(const void* f, const double* g_rho, const doub
                                   const KParams& K, hipStream_t st) {
     const int64_t cells = (int64_t)K.nx * K.ny;
     hipLaunchKernelGGL(k_moments_adjoint<S>, dim3(blocks_for(cells, 256)), dim3(256), 0, st,
-                       (const S*)f, g_rho, g_ux, g_uy, g_T, (S*)lam, K, cells);
+                       (const S*)f, g_rho, g_ux, g_uy, g_T, (double*)lam, K, cells);
     return hipGetLastError();
 }
 

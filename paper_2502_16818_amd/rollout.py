@@ -60,7 +60,7 @@ class CDBMRollout(torch.autograd.Function):
             grads.append(torch.zeros((s.ny, s.nx), dtype=torch.float64, device="cuda")
                          if g is None else g.to(torch.float64).contiguous())
         lam = s.moments_adjoint(ctx.f_final, *grads)
-        lam_next = s.empty_f()
+        lam_next = s.empty_lam()
         dtau = torch.zeros(1, dtype=torch.float64, device="cuda")
         segs = _segments(ctx.nsteps, ctx.every)
         states = [s.empty_f() for _ in range(min(ctx.every, ctx.nsteps))]
