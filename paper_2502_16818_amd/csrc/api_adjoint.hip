@@ -29,7 +29,7 @@ int step_adjoint_impl(cdbm_handle* h, const void* f_n, const void* lam_np1, void
                       double* dtau, hipStream_t st) {
     const KParams& K = h->k;
     const int nb = stage_adjoint_blocks(K);
-    hipError_t e = launch_stage<S>(f_n, nullptr, h->stage, false, K, st);
+    hipError_t e = launch_stage<S>(f_n, nullptr, h->stage, false, K, h->kdev, st);
     if (e != hipSuccess) return hip_fail(e, "stage recompute launch");
     e = launch_stage_adjoint<S>(h->stage, lam_np1, nullptr, h->lam_mid, h->tau_part, nb, 0.5, 0.0,
                                 K, st);

@@ -31,6 +31,7 @@ struct cdbm_batch {
     int* flag = nullptr;
     void* scratch = nullptr;
     int nblocks = 1;
+    bool chunked = false;   // every width and offset is a multiple of the 16-byte chunk
     StepGraph graph;
 };
 
@@ -50,9 +51,10 @@ hipError_t batch_step_once(const void* ctx, const void* fin, void* fout, hipStre
     const cdbm_batch* b = (const cdbm_batch*)ctx;
     const int n = (int)b->p.size();
     return b->precision == CDBM_MIXED
-               ? launch_batch_step<float>(fin, fout, b->d_k, b->d_off, b->d_work, n, b->nblocks, st)
+               ? launch_batch_step<float>(fin, fout, b->d_k, b->d_off, b->d_work, n, b->nblocks,
+                                          b->chunked, st)
                : launch_batch_step<double>(fin, fout, b->d_k, b->d_off, b->d_work, n, b->nblocks,
-                                           st);
+                                           b->chunked, st);
 }
 
 int check_batch_device(const cdbm_batch* b) {
@@ -148,6 +150,10 @@ int cdbm_batch_create(const cdbm_params* per_grid, int32_t ngrids, const int64_t
     const int64_t cap = (work[ngrids] + 31) / 32;
     int64_t nb = b->precision == CDBM_MIXED ? batch_blocks<float>() : batch_blocks<double>();
     b->nblocks = (int)std::max<int64_t>(1, std::min(nb, cap));
+    const int cw = b->precision == CDBM_MIXED ? 4 : 2;
+    b->chunked = true;
+    for (int g = 0; g < ngrids; ++g)
+        b->chunked = b->chunked && per_grid[g].nx % cw == 0 && f_offsets[g] % cw == 0;
     *out = b;
     return CDBM_OK;
 }

@@ -88,7 +88,10 @@ __device__ __forceinline__ Macro macro_from_parity(const Parity& g, const KParam
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) e2 = fma(K.en[c + z], g.ee[c], e2);
-    const double inv = 1.0 / rho;
+    // 1 / rho: hardware reciprocal refined by two Newton steps (error ~1 ulp)
+    double inv = __builtin_amdgcn_rcp(rho);
+    inv = fma(inv, fma(-rho, inv, 1.0), inv);
+    inv = fma(inv, fma(-rho, inv, 1.0), inv);
     Macro m;
     m.rho = rho;
     m.ux = jx * inv;
@@ -149,6 +152,66 @@ __device__ __forceinline__ void equilibrium(const Macro& m, const KParams& K, do
     }
 }
 
+// z (f - f^eq) for the 16 velocities, formed in the parity basis:
+// with g the parity combinations of f and B m-hat the (row-scaled) block
+// contraction, the scaled parity combinations of f - f^eq are
+// s_r g_r - rho (B m-hat)_r (s_r = 1/2 for axis, 1/4 for diagonal groups),
+// and unpacking them gives f_i - f_i^eq.  `zs2` = z/2 and `zs4` = z/4 fold
+// the relaxation factor into that step.
+__device__ __forceinline__ void relaxation(const Parity& g, const Macro& m, const KParams& K,
+                                           double a, double zs2, double zs4, double out[NV],
+                                           int z = 0) {
+    const double ux = m.ux, uy = m.uy, T = m.T;
+    const double ux2 = ux * ux, uy2 = uy * uy, u2 = ux2 + uy2, uxy = ux * uy;
+    const double aT = a * T;
+    const double A2 = u2 + aT + 2.0 * T;
+    const double A4 = A2 + 2.0 * T;
+    const double mee[6] = {1.0, u2 + aT, ux2 + T, uy2 + T, ux2 * A4 + T * A2, uy2 * A4 + T * A2};
+    const double moe[4] = {ux, ux * A2, ux * (ux2 + 3.0 * T), ux * (uy2 + T)};
+    const double meo[4] = {uy, uy * A2, uy * (ux2 + T), uy * (uy2 + 3.0 * T)};
+    const double moo[2] = {uxy, uxy * A4};
+    const double rz = -m.rho * (zs2 + zs2);   // -rho z
+    // scale of each parity component: ee (a, a, b, c, c, d), oe/eo (a, b, c, d), oo (b, d)
+    double tee[6], toe[4], teo[4], too[2];
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        double s = K.iee[r][z];
+#pragma unroll
+        for (int c = 1; c < 6; ++c) s = fma(K.iee[r][c + z], mee[c], s);
+        const double sc = (r == 2 || r == 5) ? zs4 : zs2;
+        tee[r] = fma(rz, s, sc * g.ee[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        double so = 0.0, se = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            so = fma(K.ioe[r][c + z], moe[c], so);
+            se = fma(K.ieo[r][c + z], meo[c], se);
+        }
+        const double sc = (r & 1) ? zs4 : zs2;
+        toe[r] = fma(rz, so, sc * g.oe[r]);
+        teo[r] = fma(rz, se, sc * g.eo[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        too[r] = fma(rz, fma(K.ioo[r][z], moo[0], K.ioo[r][1 + z] * moo[1]), zs4 * g.oo[r]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int a0 = 8 * q, d0 = 8 * q + 4;
+        out[a0 + 0] = tee[3 * q + 0] + toe[2 * q];
+        out[a0 + 2] = tee[3 * q + 0] - toe[2 * q];
+        out[a0 + 1] = tee[3 * q + 1] + teo[2 * q];
+        out[a0 + 3] = tee[3 * q + 1] - teo[2 * q];
+        const double p = tee[3 * q + 2] + teo[2 * q + 1], n = tee[3 * q + 2] - teo[2 * q + 1];
+        const double r = toe[2 * q + 1] + too[q], s = toe[2 * q + 1] - too[q];
+        out[d0 + 0] = p + r;
+        out[d0 + 1] = p - r;
+        out[d0 + 2] = n - s;
+        out[d0 + 3] = n + s;
+    }
+}
+
 // A zero the compiler cannot see through (a scalar register set by an empty
 // instruction sequence), re-created wherever constant tables are read.
 __device__ __forceinline__ int opaque_zero() {
@@ -164,53 +227,6 @@ __device__ __forceinline__ int wrap_or_clamp(int i, int n, int bc) {
         return i < 0 ? i + n : i;
     }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
-}
-
-template <typename S>
-__device__ __forceinline__ S coef_x(const KParams& K, int i);
-template <>
-__device__ __forceinline__ float coef_x<float>(const KParams& K, int i) { return K.cxf[i]; }
-template <>
-__device__ __forceinline__ double coef_x<double>(const KParams& K, int i) { return K.cx[i]; }
-template <typename S>
-__device__ __forceinline__ S coef_y(const KParams& K, int i);
-template <>
-__device__ __forceinline__ float coef_y<float>(const KParams& K, int i) { return K.cyf[i]; }
-template <>
-__device__ __forceinline__ double coef_y<double>(const KParams& K, int i) { return K.cy[i]; }
-
-// One Runge-Kutta stage at one cell.  `ld(i, ox, oy)` returns f_i at the
-// cell offset by (ox, oy) with boundary conditions applied.  Writes
-//   out_i = f_i + dt (-v_i . grad f_i) - (dt / tau) (f_i - f_i^eq)
-// which is f + dt L(f); the caller combines stages.
-template <typename S, class Ld>
-__device__ __forceinline__ void stage_cell(const Ld& ld, const KParams& K, S out[NV]) {
-    S f[NV];
-    double fd[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        f[i] = ld(i, 0, 0);
-        fd[i] = (double)f[i];
-    }
-    Parity g;
-    to_parity(fd, g);
-    const Macro m = macro_from_parity(g, K, K.inv_a);
-    double feq[NV];
-    equilibrium(m, K, K.a, feq);
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        S adv = S(0);
-        if (SX[i] > 0)
-            adv = coef_x<S>(K, i) * nnd_pos<S>(ld(i, -2, 0), ld(i, -1, 0), f[i], ld(i, 1, 0));
-        else if (SX[i] < 0)
-            adv = coef_x<S>(K, i) * nnd_neg<S>(ld(i, -1, 0), f[i], ld(i, 1, 0), ld(i, 2, 0));
-        if (SY[i] > 0)
-            adv += coef_y<S>(K, i) * nnd_pos<S>(ld(i, 0, -2), ld(i, 0, -1), f[i], ld(i, 0, 1));
-        else if (SY[i] < 0)
-            adv += coef_y<S>(K, i) * nnd_neg<S>(ld(i, 0, -1), f[i], ld(i, 0, 1), ld(i, 0, 2));
-        const S coll = (S)(K.z * (fd[i] - feq[i]));
-        out[i] = f[i] + (adv - coll);
-    }
 }
 
 }  // namespace cdbm

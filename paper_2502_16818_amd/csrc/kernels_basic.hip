@@ -5,6 +5,7 @@
 
 #include "cell.hpp"
 #include "launch.hpp"
+#include "step_fused.hpp"
 
 namespace cdbm {
 
@@ -161,12 +162,15 @@ struct GlobalLd {
     }
 };
 
-// One Runge-Kutta stage without fusion:
+// One Runge-Kutta stage without fusion, with the same per-cell arithmetic
+// as the fused step:
 //   STAGE2 == false:  out = f + dt L(f)
 //   STAGE2 == true:   out = base / 2 + (f + dt L(f)) / 2
 template <typename S, bool STAGE2>
 __global__ void __launch_bounds__(256) k_stage(const S* __restrict__ fin, const S* __restrict__ base,
-                                               S* __restrict__ fout, KParams K) {
+                                               S* __restrict__ fout,
+                                               const KParams* __restrict__ Kd) {
+    const KParams& K = *Kd;
     const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (x >= K.nx || y >= K.ny) return;
@@ -181,12 +185,12 @@ __global__ void __launch_bounds__(256) k_stage(const S* __restrict__ fin, const 
         ld.ys[o + 2] = wrap_or_clamp(y + o, K.ny, K.bcy);
     }
     S out[NV];
-    stage_cell<S>(ld, K, out);
+    stage_cell_k<S, STAGE2>(ld, K, out);
     const int64_t c = (int64_t)y * K.nx + x;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         S v = out[i];
-        if (STAGE2) v = S(0.5) * base[i * cells + c] + S(0.5) * v;
+        if (STAGE2) v = fma(S(0.5), base[i * cells + c], v);
         fout[i * cells + c] = v;
     }
 }
@@ -246,14 +250,14 @@ hipError_t launch_sum_partials(const double* part, int nblocks, int ncomp, doubl
 
 template <typename S>
 hipError_t launch_stage(const void* fin, const void* base, void* fout, bool stage2,
-                        const KParams& K, hipStream_t st) {
+                        const KParams& K, const KParams* Kd, hipStream_t st) {
     const dim3 grid(blocks_for(K.nx, 64), blocks_for(K.ny, 4));
     if (stage2)
         hipLaunchKernelGGL((k_stage<S, true>), grid, dim3(256), 0, st, (const S*)fin,
-                           (const S*)base, (S*)fout, K);
+                           (const S*)base, (S*)fout, Kd);
     else
         hipLaunchKernelGGL((k_stage<S, false>), grid, dim3(256), 0, st, (const S*)fin,
-                           (const S*)base, (S*)fout, K);
+                           (const S*)base, (S*)fout, Kd);
     return hipGetLastError();
 }
 
@@ -266,7 +270,7 @@ hipError_t launch_stage(const void* fin, const void* base, void* fout, bool stag
     template hipError_t launch_totals<S>(const void*, double*, int, double*, const KParams&,   \
                                          hipStream_t);                                         \
     template hipError_t launch_stage<S>(const void*, const void*, void*, bool, const KParams&, \
-                                        hipStream_t);
+                                        const KParams*, hipStream_t);
 CDBM_INSTANTIATE(float)
 CDBM_INSTANTIATE(double)
 #undef CDBM_INSTANTIATE

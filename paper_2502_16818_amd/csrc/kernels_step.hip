@@ -11,12 +11,12 @@ namespace cdbm {
 
 namespace {
 
-template <typename S>
-__global__ void __launch_bounds__(FUSED_NT) k_step_fused(const S* __restrict__ fin,
-                                                         S* __restrict__ fout,
-                                                         const KParams* __restrict__ Kd) {
-    __shared__ S F0[FUSED_SLOTS * NV * FUSED_W0];
-    __shared__ S F1[FUSED_SLOTS * NV * FUSED_W1];
+template <typename S, bool VEC>
+__global__ void __launch_bounds__(FusedGeom<S>::NT) k_step_fused(const S* __restrict__ fin,
+                                                                 S* __restrict__ fout,
+                                                                 const KParams* __restrict__ Kd) {
+    __shared__ __attribute__((aligned(16))) S F0[FusedGeom<S>::F0_ELEMS];
+    __shared__ __attribute__((aligned(16))) S F1[FusedGeom<S>::F1_ELEMS];
     const KParams& K = *Kd;
     const int nstrips = (K.nx + FUSED_TX - 1) / FUSED_TX;
     // Block b takes the b-th of gridDim.x equal, contiguous pieces of the
@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(FUSED_NT) k_step_fused(const S* __restrict__ f
         const int s = (int)(u / K.ny);
         const int ya = (int)(u - (int64_t)s * K.ny);
         const int yb = (int)min((int64_t)K.ny, (int64_t)ya + (u1 - u));
-        fused_strip<S>(fin, fout, K, s * FUSED_TX, ya, yb, F0, F1);
+        fused_strip<S, VEC>(fin, fout, K, s * FUSED_TX, ya, yb, F0, F1);
         u += yb - ya;
     }
 }
@@ -43,7 +43,7 @@ int fused_grid_blocks(const KParams& K) {
         if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
         cus = prop.multiProcessorCount;
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_fused<S>, FUSED_NT, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_fused<S, true>, FusedGeom<S>::NT, 0) !=
                 hipSuccess ||
             nb < 1)
             nb = 1;
@@ -64,8 +64,12 @@ template <typename S>
 hipError_t launch_step_fused(const void* fin, void* fout, const KParams& K, const KParams* Kd,
                              hipStream_t st) {
     const int g = fused_grid_blocks<S>(K);
-    hipLaunchKernelGGL(k_step_fused<S>, dim3(g), dim3(FUSED_NT), 0, st, (const S*)fin, (S*)fout,
-                       Kd);
+    if (fused_chunked<S>(K.nx, fin, fout))
+        hipLaunchKernelGGL((k_step_fused<S, true>), dim3(g), dim3(FusedGeom<S>::NT), 0, st,
+                           (const S*)fin, (S*)fout, Kd);
+    else
+        hipLaunchKernelGGL((k_step_fused<S, false>), dim3(g), dim3(FusedGeom<S>::NT), 0, st,
+                           (const S*)fin, (S*)fout, Kd);
     return hipGetLastError();
 }
 

@@ -26,7 +26,7 @@ hipError_t launch_sum_partials(const double* part, int nblocks, int ncomp, doubl
                                hipStream_t st);
 template <typename S>
 hipError_t launch_stage(const void* fin, const void* base, void* fout, bool stage2,
-                        const KParams& K, hipStream_t st);
+                        const KParams& K, const KParams* Kd, hipStream_t st);
 
 // Fused two-stage step (kernels_step.hip).  K: host copy (launch geometry);
 // Kd: the same constants in device memory (read by the kernel).
@@ -56,7 +56,10 @@ hipError_t launch_accumulate_scalar(const double* part, int nblocks, double scal
 template <typename S>
 int batch_blocks();
 template <typename S>
+// chunked: every grid's width and element offset is a multiple of the
+// 16-byte chunk (the buffers' alignment is checked at launch).
 hipError_t launch_batch_step(const void* fin, void* fout, const KParams* Ks, const int64_t* f_off,
-                             const int64_t* work_start, int ngrids, int nblocks, hipStream_t st);
+                             const int64_t* work_start, int ngrids, int nblocks, bool chunked,
+                             hipStream_t st);
 
 }  // namespace cdbm

@@ -214,6 +214,10 @@ int build_params(const cdbm_params& p, KParams& k, std::string& err) {
         k.cy[i] = -p.dt * vy[i] / p.dy;
         k.cxf[i] = (float)k.cx[i];
         k.cyf[i] = (float)k.cy[i];
+        k.cxh[i] = 0.5 * k.cx[i];
+        k.cyh[i] = 0.5 * k.cy[i];
+        k.cxhf[i] = (float)k.cxh[i];
+        k.cyhf[i] = (float)k.cyh[i];
     }
     k.a = 2.0 + extra_dof(p.gamma);
     k.inv_a = 1.0 / k.a;

@@ -49,6 +49,8 @@ struct KParams {
     double vx[NV], vy[NV], eta2[NV];
     double cx[NV], cy[NV];     // -dt v_ix / dx and -dt v_iy / dy
     float cxf[NV], cyf[NV];
+    double cxh[NV], cyh[NV];   // the same halved (the second Runge-Kutta stage)
+    float cxhf[NV], cyhf[NV];
     double a;                  // D + I
     double inv_a;              // 1 / (D + I)
     double z;                  // dt / tau

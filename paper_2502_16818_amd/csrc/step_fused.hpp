@@ -2,16 +2,19 @@
 // over HBM).
 //
 // A block owns a strip of TX = 60 output columns and streams down the grid
-// in y, R = 4 rows per iteration, keeping two ring buffers in LDS:
-//   F0: f^n rows, 2R slots of TX + 8 columns (x halo of 4 each side);
-//   F1: f^(1) = f^n + dt L(f^n) rows, 2R slots of TX + 4 columns.
-// Iteration t (rows relative to the strip start y0):
-//   load  f^n  rows [y0 - 4 + tR,   y0 - 4 + (t+1)R)   (global -> registers -> F0)
-//   stage 1    rows [y0 - 2 + (t-1)R, y0 - 2 + tR)      (F0 -> F1; one cell per thread)
-//   stage 2    rows [y0 + (t-2)R,   y0 + (t-1)R)        (F1, F0 -> f^{n+1} in HBM)
-// so each f value crosses HBM once in and once out per step; stage 1 is
-// recomputed only on the 2-column x halo (64 columns for 60 outputs).  The
-// global loads of iteration t+1 are issued before the stages of iteration t.
+// in y, R rows per iteration (one wave per row), keeping two ring buffers of
+// R + 4 rows in LDS:
+//   F0: f^n rows, TX + 8 columns (x halo of 4 each side);
+//   F1: f^(1) = f^n + dt L(f^n) rows, TX + 4 columns.
+// Iteration t (rows relative to the segment start):
+//   load  f^n    rows [4 + (t-2)R, 4 + (t-1)R)   (global -> registers -> F0)
+//   stage 1      rows [2 + (t-2)R, 2 + (t-1)R)   (F0 -> F1; one cell per thread)
+//   stage 2      rows [(t-2)R, (t-1)R)           (F1, F0 -> f^{n+1} in HBM)
+// Each stage runs just two rows behind what it needs, so R + 4 rows of each
+// ring are live at once; each f value crosses HBM once in and once out per
+// step, and stage 1 is recomputed only on the 2-column x halo (64 columns
+// for 60 outputs).  The global loads of iteration t+1 are issued before the
+// stages of iteration t.
 //
 // Boundary conditions: f^n ghost cells are loaded through the periodic wrap
 // or the edge clamp, which is exactly the ghost fill of the scheme.  For a
@@ -22,29 +25,53 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "cell.hpp"
 
 namespace cdbm {
 
 constexpr int FUSED_TX = 60;               // output columns per strip
-constexpr int FUSED_R = 4;                 // rows per iteration
 constexpr int FUSED_W0 = FUSED_TX + 8;     // F0 row width
 constexpr int FUSED_W1 = FUSED_TX + 4;     // F1 row width (= 64 = one wave)
-constexpr int FUSED_SLOTS = 2 * FUSED_R;   // ring depth
-constexpr int FUSED_NT = FUSED_R * FUSED_W1;   // 256 threads
+
+// Rows per iteration: one wave per row.  The ring depth R + 4 must be a
+// power of two.  FP32 uses 12 (768 threads, 132 KB of LDS, one block per
+// compute unit, three waves per SIMD); FP64 needs twice the LDS per row and
+// uses 4.
+template <typename S>
+struct FusedRows;
+template <>
+struct FusedRows<float> {
+    static constexpr int R = 12;
+};
+template <>
+struct FusedRows<double> {
+    static constexpr int R = 4;
+};
 
 template <typename S>
-__device__ __forceinline__ S coef_x(const KParams& K, int i, int z);
-template <>
-__device__ __forceinline__ float coef_x<float>(const KParams& K, int i, int z) { return K.cxf[i + z]; }
-template <>
-__device__ __forceinline__ double coef_x<double>(const KParams& K, int i, int z) { return K.cx[i + z]; }
-template <typename S>
-__device__ __forceinline__ S coef_y(const KParams& K, int i, int z);
-template <>
-__device__ __forceinline__ float coef_y<float>(const KParams& K, int i, int z) { return K.cyf[i + z]; }
-template <>
-__device__ __forceinline__ double coef_y<double>(const KParams& K, int i, int z) { return K.cy[i + z]; }
+struct FusedGeom {
+    static constexpr int R = FusedRows<S>::R;
+    static constexpr int SLOTS = R + 4;
+    static constexpr int NT = R * 64;
+    static constexpr int F0_ELEMS = SLOTS * NV * FUSED_W0;
+    static constexpr int F1_ELEMS = SLOTS * NV * FUSED_W1;
+    static_assert((SLOTS & (SLOTS - 1)) == 0, "ring depth must be a power of two");
+};
+
+// NND coefficients -dt v_ir / dr of a stage: HALF selects the halved ones of
+// the second Runge-Kutta stage.
+template <typename S, bool HALF>
+__device__ __forceinline__ S stage_coef_x(const KParams& K, int i, int z) {
+    if constexpr (sizeof(S) == 4) return HALF ? K.cxhf[i + z] : K.cxf[i + z];
+    else return HALF ? K.cxh[i + z] : K.cx[i + z];
+}
+template <typename S, bool HALF>
+__device__ __forceinline__ S stage_coef_y(const KParams& K, int i, int z) {
+    if constexpr (sizeof(S) == 4) return HALF ? K.cyhf[i + z] : K.cyf[i + z];
+    else return HALF ? K.cyh[i + z] : K.cy[i + z];
+}
 
 // Reads of one ring buffer around one cell.  Offsets are compile-time after
 // unrolling; only one of (ox, oy) is ever nonzero.
@@ -59,9 +86,12 @@ struct RingLd {
     }
 };
 
-// One stage at one cell, f + dt L(f), with every run constant read from K at
-// an opaque zero offset (see opaque_zero).
-template <typename S, class Ld>
+// One stage at one cell with every run constant read from K at an opaque
+// zero offset (see opaque_zero).  First stage (HALF = false): returns
+// f + dt L(f).  Second stage (HALF = true): returns (f + dt L(f)) / 2, with
+// the 1/2 folded into the coefficients, so that the Heun combination is
+// f^n / 2 plus the result.
+template <typename S, bool HALF, class Ld>
 __device__ __forceinline__ void stage_cell_k(const Ld& ld, const KParams& K, S out[NV]) {
     const int z = opaque_zero();
     S f[NV];
@@ -74,23 +104,37 @@ __device__ __forceinline__ void stage_cell_k(const Ld& ld, const KParams& K, S o
     Parity g;
     to_parity(fd, g);
     const Macro m = macro_from_parity(g, K, (&K.inv_a)[z], z);
-    double feq[NV];
-    equilibrium(m, K, (&K.a)[z], feq, z);
-    const double zr = (&K.z)[z];
+    const double zr = (&K.z)[z] * (HALF ? 0.5 : 1.0);
+    double coll[NV];
+    relaxation(g, m, K, (&K.a)[z], 0.5 * zr, 0.25 * zr, coll, z);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         S adv = S(0);
         if (SX[i] > 0)
-            adv = coef_x<S>(K, i, z) * nnd_pos<S>(ld(i, -2, 0), ld(i, -1, 0), f[i], ld(i, 1, 0));
+            adv = stage_coef_x<S, HALF>(K, i, z) *
+                  nnd_pos<S>(ld(i, -2, 0), ld(i, -1, 0), f[i], ld(i, 1, 0));
         else if (SX[i] < 0)
-            adv = coef_x<S>(K, i, z) * nnd_neg<S>(ld(i, -1, 0), f[i], ld(i, 1, 0), ld(i, 2, 0));
+            adv = stage_coef_x<S, HALF>(K, i, z) *
+                  nnd_neg<S>(ld(i, -1, 0), f[i], ld(i, 1, 0), ld(i, 2, 0));
         if (SY[i] > 0)
-            adv += coef_y<S>(K, i, z) * nnd_pos<S>(ld(i, 0, -2), ld(i, 0, -1), f[i], ld(i, 0, 1));
+            adv += stage_coef_y<S, HALF>(K, i, z) *
+                   nnd_pos<S>(ld(i, 0, -2), ld(i, 0, -1), f[i], ld(i, 0, 1));
         else if (SY[i] < 0)
-            adv += coef_y<S>(K, i, z) * nnd_neg<S>(ld(i, 0, -1), f[i], ld(i, 0, 1), ld(i, 0, 2));
-        const S coll = (S)(zr * (fd[i] - feq[i]));
-        out[i] = f[i] + (adv - coll);
+            adv += stage_coef_y<S, HALF>(K, i, z) *
+                   nnd_neg<S>(ld(i, 0, -1), f[i], ld(i, 0, 1), ld(i, 0, 2));
+        const S d = adv - (S)coll[i];
+        out[i] = HALF ? fma(S(0.5), f[i], d) : f[i] + d;
     }
+}
+
+// Block barrier that orders LDS traffic only.  The waves of a block share
+// data through LDS alone (f^n is read-only, each f^{n+1} element is written
+// by one thread), so global loads and stores may stay in flight across it;
+// __syncthreads() would also drain them at every barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // Source row of a (possibly ghost) row index: periodic wrap or edge clamp.
@@ -106,109 +150,211 @@ __device__ __forceinline__ int source_row(int r, int n, int bc) {
 
 __device__ __forceinline__ int map_index(int i, int n, int bc) { return wrap_or_clamp(i, n, bc); }
 
+// 16-byte vector of the storage type (4 floats or 2 doubles).
+template <typename S>
+struct Chunk;
+template <>
+struct Chunk<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Chunk<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+
+// Elements per 16-byte chunk of the chunked form.
+template <typename S>
+constexpr int fused_chunk_elems() {
+    return 16 / (int)sizeof(S);
+}
+inline bool aligned16(const void* a, const void* b) {
+    return (((uintptr_t)a | (uintptr_t)b) & 15) == 0;
+}
+// Can a grid of width nx between these buffers use the chunked form?
+template <typename S>
+inline bool fused_chunked(int nx, const void* fin, const void* fout) {
+    return nx % fused_chunk_elems<S>() == 0 && aligned16(fin, fout);
+}
+
 // Advance rows [ya, yb) of the strip starting at column x0 of one grid.
 // All threads of the block must call this together (it synchronizes).
-template <typename S>
+//
+// VEC = false: every lane moves one column of each row (any grid).
+// VEC = true: rows move between HBM and LDS in 16-byte chunks spread over
+// the lanes of the wave; needs nx to be a multiple of the chunk width and
+// 16-byte aligned buffers (fused_chunked), so that every chunk of loaded
+// columns lies inside one row.  A chunk left or right of the grid takes its
+// periodic image; on a zero-gradient side those ghost columns are never read,
+// because both stages redirect ghost-column reads to the edge column.  The
+// stage-2 result of a row is first written to the F0 slot of that row, which
+// no other wave reads before its refill behind the next barrier, and is
+// stored from there in chunks.
+template <typename S, bool VEC>
 __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __restrict__ fout,
                                             const KParams& K, int x0, int ya, int yb, S* F0,
                                             S* F1) {
+    using G = FusedGeom<S>;
+    using V = typename Chunk<S>::type;
+    constexpr int R = G::R;
+    constexpr int SLOTS = G::SLOTS;
+    constexpr int CW = 16 / (int)sizeof(S);        // elements per chunk
+    constexpr int LCH = FUSED_W0 / CW;             // chunks per loaded velocity row
+    constexpr int NLD = (NV * LCH + 63) / 64;      // chunk loads per lane and row
+    constexpr int SCH = FUSED_TX / CW;             // chunks per stored velocity row
+    constexpr int NST = (NV * SCH + 63) / 64;      // chunk stores per lane and row
+    static_assert(FUSED_W0 % CW == 0 && FUSED_TX % CW == 0 && 4 % CW == 0, "chunk geometry");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // 0..3, uniform
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // 0..R-1, uniform
     const int nx = K.nx, ny = K.ny, bcx = K.bcx, bcy = K.bcy;
     const int64_t cells = (int64_t)nx * ny;
-
-    // global columns this lane loads into F0 (lanes 0..63, plus 64..67 on lanes 0..3)
-    const int gc_a = map_index(x0 - 4 + lane, nx, bcx);
-    const int gc_b = map_index(x0 - 4 + 64 + (lane & 3), nx, bcx);
-
-    // ring slot of a row: rows are >= ya - 4 - 2R when used
-    const int yref0 = ya - 4 - FUSED_SLOTS;
-    const int yref1 = ya - 2 - FUSED_SLOTS;
-    auto slot0 = [&](int r) { return (r - yref0) & (FUSED_SLOTS - 1); };
-    auto slot1 = [&](int r) { return (r - yref1) & (FUSED_SLOTS - 1); };
-
     const int nrows = yb - ya;
-    const int niter = (nrows + FUSED_R - 1) / FUSED_R + 2;
 
-    // each wave loads 16 of the 64 (row, velocity) lines of an iteration
-    constexpr int LINES = FUSED_R * NV / 4;   // per wave
-    S pre_a[LINES], pre_b[LINES];
+    // ring slot of a row given relative to ya (rows >= -4 - R are ever used)
+    auto slot = [&](int q) { return (q + 4 * SLOTS) & (SLOTS - 1); };
+
+    // Chunk c = k * 64 + lane of a row: velocity c / per_row, chunk c % per_row.
+    // Lanes past the last chunk repeat it (the same value to the same place).
+    // With FP32 storage, z is an opaque zero, so the indices are recomputed
+    // at each use instead of being held in registers through the stages
+    // (FP64 runs one wave per SIMD and has the registers to keep them).
+    auto chunk = [&](int k, int per_row, int z, int& i, int& j) {
+        const int c = min(k * 64 + lane + z, NV * per_row - 1);
+        i = c / per_row;
+        j = c - i * per_row;
+    };
+    // strips whose loaded columns reach past a side of the grid
+    const bool edge = x0 < 4 || x0 + FUSED_W0 - 4 > nx;
+
+    // wave w loads row 4 + (t-2)R + w (all 16 velocities) at iteration t;
+    // only rows -4 .. nrows+3 are needed
+    constexpr int NPRE = VEC ? NLD : 2 * NV;
+    using P = typename std::conditional<VEC, V, S>::type;
+    P pre[NPRE];
+    // per-column form: global columns this lane loads into F0 (lanes 0..63,
+    // plus 64..67 on lanes 0..3)
+    const int gc_a = VEC ? 0 : map_index(x0 - 4 + lane, nx, bcx);
+    const int gc_b = VEC ? 0 : map_index(x0 - 4 + 64 + (lane & 3), nx, bcx);
+    auto load_row = [&](int t) { return 4 + (t - 2) * R + wave; };
+    auto wanted = [&](int q) { return q >= -4 && q < nrows + 4; };
     auto issue_loads = [&](int t) {
-        const int rbase = ya - 4 + t * FUSED_R;
+        const int q = load_row(t);
+        if (!wanted(q)) return;
+        const S* src = fin + (int64_t)source_row(ya + q, ny, bcy) * nx;
+        if constexpr (VEC) {
+            const int z = sizeof(S) == 4 ? opaque_zero() : 0;
 #pragma unroll
-        for (int k = 0; k < LINES; ++k) {
-            const int line = wave * LINES + k;       // 0..63
-            const int rr = line / NV, i = line % NV;
-            const int gr = source_row(rbase + rr, ny, bcy);
-            const S* src = fin + (int64_t)i * cells + (int64_t)gr * nx;
-            pre_a[k] = src[gc_a];
-            pre_b[k] = (lane < 4) ? src[gc_b] : S(0);
+            for (int k = 0; k < NLD; ++k) {
+                int i, j;
+                chunk(k, LCH, z, i, j);
+                int cs = x0 - 4 + j * CW;
+                if (edge) {
+                    cs %= nx;
+                    if (cs < 0) cs += nx;
+                }
+                pre[k] = *(const V*)(src + (int64_t)i * cells + cs);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                pre[i] = src[(int64_t)i * cells + gc_a];
+                pre[NV + i] = (lane < 4) ? src[(int64_t)i * cells + gc_b] : S(0);
+            }
         }
     };
     auto store_loads = [&](int t) {
-        const int rbase = ya - 4 + t * FUSED_R;
+        const int q = load_row(t);
+        if (!wanted(q)) return;
+        S* dst = F0 + slot(q) * NV * FUSED_W0;
+        if constexpr (VEC) {
+            // chunk c sits at element c * CW of the slot (FUSED_W0 = LCH * CW)
 #pragma unroll
-        for (int k = 0; k < LINES; ++k) {
-            const int line = wave * LINES + k;
-            const int rr = line / NV, i = line % NV;
-            S* dst = F0 + (slot0(rbase + rr) * NV + i) * FUSED_W0;
-            dst[lane] = pre_a[k];
-            if (lane < 4) dst[64 + lane] = pre_b[k];
+            for (int k = 0; k < NLD; ++k)
+                *(V*)(dst + min(k * 64 + lane, NV * LCH - 1) * CW) = pre[k];
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                dst[i * FUSED_W0 + lane] = pre[i];
+                if (lane < 4) dst[i * FUSED_W0 + 64 + lane] = pre[NV + i];
+            }
         }
     };
 
-    issue_loads(0);
-    for (int t = 0; t < niter; ++t) {
-        __syncthreads();   // previous stages are done with the slots being overwritten
+    // first iteration whose loads reach row -4; stage 2 finishes at t_end
+    const int t0 = 2 - (8 + R - 1) / R;
+    const int t_end = (nrows + R - 1) / R + 1;
+    issue_loads(t0);
+    for (int t = t0; t <= t_end; ++t) {
+        lds_barrier();   // the stages of iteration t-1 are done with the slots reused below
         store_loads(t);
-        if (t + 1 < niter) issue_loads(t + 1);
-        __syncthreads();
+        if (t < t_end) issue_loads(t + 1);
+        lds_barrier();
 
-        // stage 1: f^(1) at row r1, column x0 - 2 + lane
-        if (t >= 1) {
-            const int r1 = ya - 2 + (t - 1) * FUSED_R + wave;
+        // stage 1: f^(1) at row q1, column x0 - 2 + lane
+        const int q1 = 2 + (t - 2) * R + wave;
+        if (q1 >= -2 && q1 < nrows + 2) {
             RingLd<S, FUSED_W0> ld;
             ld.ring = F0;
+            const int x1 = x0 - 2 + lane;
 #pragma unroll
             for (int o = -2; o <= 2; ++o) {
-                ld.slot[o + 2] = slot0(r1 + o);
-                ld.col[o + 2] = lane + 2 + o;
+                ld.slot[o + 2] = slot(q1 + o);
+                ld.col[o + 2] = (bcx == CDBM_ZERO_GRADIENT) ? min(max(x1 + o, 0), nx - 1) - (x0 - 4)
+                                                            : lane + 2 + o;
             }
             S out[NV];
-            stage_cell_k<S>(ld, K, out);
-            S* dst = F1 + slot1(r1) * NV * FUSED_W1 + lane;
+            stage_cell_k<S, false>(ld, K, out);
+            S* dst = F1 + slot(q1) * NV * FUSED_W1 + lane;
 #pragma unroll
             for (int i = 0; i < NV; ++i) dst[i * FUSED_W1] = out[i];
         }
-        __syncthreads();
+        lds_barrier();
 
-        // stage 2: f^{n+1} at row r2, column x0 + lane
-        if (t >= 2) {
-            const int r2 = ya + (t - 2) * FUSED_R + wave;
+        // stage 2: f^{n+1} at row q2, column x0 + lane
+        const int q2 = (t - 2) * R + wave;
+        if (q2 >= 0 && q2 < nrows) {
+            const int r2 = ya + q2;
             const int x = x0 + lane;
-            const bool active = lane < FUSED_TX && x < nx && r2 < yb;
             RingLd<S, FUSED_W1> ld;
             ld.ring = F1;
 #pragma unroll
             for (int o = -2; o <= 2; ++o) {
                 const int rr = (bcy == CDBM_ZERO_GRADIENT) ? min(max(r2 + o, 0), ny - 1) : r2 + o;
                 const int cc = (bcx == CDBM_ZERO_GRADIENT) ? min(max(x + o, 0), nx - 1) : x + o;
-                ld.slot[o + 2] = slot1(rr);
+                ld.slot[o + 2] = slot(rr - ya);
                 ld.col[o + 2] = min(max(cc - (x0 - 2), 0), FUSED_W1 - 1);
             }
             S out[NV];
-            stage_cell_k<S>(ld, K, out);
-            if (active) {
-                const S* fn = F0 + slot0(r2) * NV * FUSED_W0 + lane + 4;
+            stage_cell_k<S, true>(ld, K, out);
+            S* row = F0 + slot(q2) * NV * FUSED_W0 + 4;   // f^n of row q2 from column x0
+            if constexpr (VEC) {
+                // each lane reads and then overwrites only its own column here
+#pragma unroll
+                for (int i = 0; i < NV; ++i)
+                    row[i * FUSED_W0 + lane] = fma(S(0.5), row[i * FUSED_W0 + lane], out[i]);
+                // the chunks below gather columns written by other lanes
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+                S* dst = fout + (int64_t)r2 * nx + x0;
+                const int z = sizeof(S) == 4 ? opaque_zero() : 0;
+#pragma unroll
+                for (int k = 0; k < NST; ++k) {
+                    int i, j;
+                    chunk(k, SCH, z, i, j);
+                    if (x0 + j * CW < nx)
+                        *(V*)(dst + (int64_t)i * cells + j * CW) =
+                            *(const V*)(row + i * FUSED_W0 + j * CW);
+                }
+            } else if (lane < FUSED_TX && x < nx) {
                 S* dst = fout + (int64_t)r2 * nx + x;
 #pragma unroll
                 for (int i = 0; i < NV; ++i)
-                    dst[(int64_t)i * cells] = S(0.5) * fn[i * FUSED_W0] + S(0.5) * out[i];
+                    dst[(int64_t)i * cells] = fma(S(0.5), row[i * FUSED_W0 + lane], out[i]);
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
 }
 
 }  // namespace cdbm

@@ -18,11 +18,19 @@ def _params(runs, precision):
                         precision) for r in runs]
 
 
-def _mixed_set():
+# Widths that rule out the 16-byte-chunk form of the batch kernel, and widths
+# that are all multiples of four (chunked form in both precisions).
+SIZE_SETS = {
+    "ragged": [(37, 23), (130, 7), (5, 61), (64, 64), (1, 1), (200, 1)],
+    "chunked": [(36, 23), (132, 7), (8, 61), (64, 64), (4, 1), (200, 1)],
+}
+
+
+def _mixed_set(sizes="ragged"):
     """Grids of uneven size with their own gamma, tau, dt and boundary conditions."""
     rng = np.random.default_rng(21)
     runs = []
-    for k, (nx, ny) in enumerate([(37, 23), (130, 7), (5, 61), (64, 64), (1, 1), (200, 1)]):
+    for k, (nx, ny) in enumerate(SIZE_SETS[sizes]):
         r = W.random_periodic(nx, ny, seed=30 + k, dt=float(rng.uniform(2e-5, 1e-4)),
                               tau=float(10 ** rng.uniform(-4.3, -3.5)),
                               gamma=float(rng.uniform(1.1, 1.67)))
@@ -32,9 +40,10 @@ def _mixed_set():
     return runs
 
 
-def test_batch_fp64_matches_oracle_per_grid():
+@pytest.mark.parametrize("sizes", sorted(SIZE_SETS))
+def test_batch_fp64_matches_oracle_per_grid(sizes):
     from paper_2502_16818_amd import Batch
-    runs = _mixed_set()
+    runs = _mixed_set(sizes)
     b = Batch(_params(runs, FP64))
     f = b.init([(r.rho, r.ux, r.uy, r.T) for r in runs])
     nsteps = 5
@@ -45,10 +54,11 @@ def test_batch_fp64_matches_oracle_per_grid():
         assert rel_max(to_np(b.view(out, k)), ref.numpy()) < 1e-12
 
 
+@pytest.mark.parametrize("sizes", sorted(SIZE_SETS))
 @pytest.mark.parametrize("precision", [FP64, MIXED])
-def test_batch_is_bitwise_equal_to_single_grid_runs(precision):
+def test_batch_is_bitwise_equal_to_single_grid_runs(precision, sizes):
     from paper_2502_16818_amd import Batch, Solver
-    runs = _mixed_set()
+    runs = _mixed_set(sizes)
     b = Batch(_params(runs, precision))
     f = b.init([(r.rho, r.ux, r.uy, r.T) for r in runs])
     nsteps = 40          # long enough to replay the captured graph

@@ -32,7 +32,23 @@ def _cases():
     zg.bc_y = W.ZERO_GRADIENT
     tiny = W.random_periodic(3, 2, seed=6, dt=1e-4, tau=1e-4)
     one = W.random_periodic(1, 1, seed=7, dt=1e-4, tau=1e-4)
-    return [sod, lax, rnd, tg, acl, zg, tiny, one]
+    return [sod, lax, rnd, tg, acl, zg, tiny, one] + _chunked_cases()
+
+
+def _chunked_cases():
+    """Widths that are multiples of four: the step moves rows in 16-byte
+    chunks (both precisions), including strips whose loaded columns wrap or
+    meet a zero-gradient side, and grids narrower than one strip."""
+    rnd4 = W.random_periodic(136, 23, seed=11, dt=1e-4, tau=2e-4)   # 3 strips, ragged tail
+    zg4 = W.random_periodic(68, 9, seed=12, dt=1e-4, tau=1e-4)
+    zg4.bc_x = W.ZERO_GRADIENT
+    zg4.bc_y = W.ZERO_GRADIENT
+    zgx = W.random_periodic(124, 11, seed=13, dt=1e-4, tau=1e-4)
+    zgx.bc_x = W.ZERO_GRADIENT
+    narrow = W.random_periodic(8, 5, seed=14, dt=1e-4, tau=1e-4)
+    for r, tag in ((rnd4, "rnd4"), (zg4, "zg4"), (zgx, "zgx"), (narrow, "narrow")):
+        r.name = f"{r.name}_{tag}"
+    return [rnd4, zg4, zgx, narrow]
 
 
 @pytest.mark.parametrize("run", _cases(), ids=lambda r: r.name)
@@ -96,7 +112,7 @@ def test_sod_tube_full_run_fp64():
     assert max(errs.values()) < 1e-12
 
 
-@pytest.mark.parametrize("run", _cases()[:6], ids=lambda r: r.name)
+@pytest.mark.parametrize("run", _cases()[:6] + _chunked_cases(), ids=lambda r: r.name)
 def test_step_mixed_against_fp64_oracle(run):
     s = _solver(run, MIXED)
     f = s.init(run.rho, run.ux, run.uy, run.T)
