@@ -122,7 +122,8 @@ int cdbm_batch_create(const cdbm_params* per_grid, int32_t ngrids, const int64_t
 
     std::vector<int64_t> work(ngrids + 1, 0);
     for (int g = 0; g < ngrids; ++g) {
-        const int64_t strips = (per_grid[g].nx + FUSED_TX - 1) / FUSED_TX;
+        const int tx = strip_width(b->precision);
+        const int64_t strips = (per_grid[g].nx + tx - 1) / tx;
         work[g + 1] = work[g] + strips * per_grid[g].ny;
     }
     hipError_t e = hipGetDevice(&b->device);
@@ -150,10 +151,13 @@ int cdbm_batch_create(const cdbm_params* per_grid, int32_t ngrids, const int64_t
     const int64_t cap = (work[ngrids] + 31) / 32;
     int64_t nb = b->precision == CDBM_MIXED ? batch_blocks<float>() : batch_blocks<double>();
     b->nblocks = (int)std::max<int64_t>(1, std::min(nb, cap));
+    // the chunked form of the step (16-byte chunks, 32-bit offsets within a grid)
     const int cw = b->precision == CDBM_MIXED ? 4 : 2;
+    const uint64_t esz = b->precision == CDBM_MIXED ? 4 : 8;
     b->chunked = true;
     for (int g = 0; g < ngrids; ++g)
-        b->chunked = b->chunked && per_grid[g].nx % cw == 0 && f_offsets[g] % cw == 0;
+        b->chunked = b->chunked && per_grid[g].nx % cw == 0 && f_offsets[g] % cw == 0 &&
+                     (uint64_t)NV * per_grid[g].nx * per_grid[g].ny * esz <= (uint64_t(1) << 32);
     *out = b;
     return CDBM_OK;
 }

@@ -8,21 +8,22 @@
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
-#include "step_fused.hpp"
+#include "step_wide.hpp"
 
 namespace cdbm {
 
 namespace {
 
 template <typename S, bool VEC>
-__global__ void __launch_bounds__(FusedGeom<S>::NT) k_batch_step(const S* __restrict__ fin,
+__global__ void __launch_bounds__(StripKernel<S>::NT) k_batch_step(const S* __restrict__ fin,
                                                          S* __restrict__ fout,
                                                          const KParams* __restrict__ Ks,
                                                          const int64_t* __restrict__ f_off,
                                                          const int64_t* __restrict__ work_start,
                                                          int ngrids) {
-    __shared__ __attribute__((aligned(16))) S F0[FusedGeom<S>::F0_ELEMS];
-    __shared__ __attribute__((aligned(16))) S F1[FusedGeom<S>::F1_ELEMS];
+    using SK = StripKernel<S>;
+    __shared__ __attribute__((aligned(16))) S F0[SK::F0_ELEMS];
+    __shared__ __attribute__((aligned(16))) S F1[SK::F1_ELEMS];
     const int64_t total = work_start[ngrids];
     const int64_t u1 = total * (blockIdx.x + 1) / gridDim.x;
     int64_t u = total * blockIdx.x / gridDim.x;
@@ -34,7 +35,7 @@ __global__ void __launch_bounds__(FusedGeom<S>::NT) k_batch_step(const S* __rest
         const int s = (int)(v / K.ny);
         const int ya = (int)(v - (int64_t)s * K.ny);
         const int yb = (int)min((int64_t)K.ny, (int64_t)ya + (u1 - u));
-        fused_strip<S, VEC>(fin + f_off[g], fout + f_off[g], K, s * FUSED_TX, ya, yb, F0, F1);
+        SK::template run<VEC>(fin + f_off[g], fout + f_off[g], K, s * SK::TX, ya, yb, F0, F1);
         u += yb - ya;
     }
 }
@@ -50,7 +51,7 @@ int batch_blocks() {
         if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
             return 256;
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<S, true>, FusedGeom<S>::NT, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<S, true>, StripKernel<S>::NT, 0) !=
                 hipSuccess ||
             nb < 1)
             nb = 1;
@@ -64,12 +65,16 @@ hipError_t launch_batch_step(const void* fin, void* fout, const KParams* Ks, con
                              const int64_t* work_start, int ngrids, int nblocks, bool chunked,
                              hipStream_t st) {
     if (chunked && aligned16(fin, fout))
-        hipLaunchKernelGGL((k_batch_step<S, true>), dim3(nblocks), dim3(FusedGeom<S>::NT), 0, st,
+        hipLaunchKernelGGL((k_batch_step<S, true>), dim3(nblocks), dim3(StripKernel<S>::NT), 0, st,
                            (const S*)fin, (S*)fout, Ks, f_off, work_start, ngrids);
     else
-        hipLaunchKernelGGL((k_batch_step<S, false>), dim3(nblocks), dim3(FusedGeom<S>::NT), 0, st,
+        hipLaunchKernelGGL((k_batch_step<S, false>), dim3(nblocks), dim3(StripKernel<S>::NT), 0, st,
                            (const S*)fin, (S*)fout, Ks, f_off, work_start, ngrids);
     return hipGetLastError();
+}
+
+int strip_width(int precision) {
+    return precision == CDBM_MIXED ? StripKernel<float>::TX : StripKernel<double>::TX;
 }
 
 template int batch_blocks<float>();

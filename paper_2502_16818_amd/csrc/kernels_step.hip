@@ -1,61 +1,82 @@
-// Fused CDBM time step on one grid: a persistent launch whose blocks each
-// take an equal, contiguous share of the grid's (strip, row) sequence, so
-// that every block streams down as few strips as possible and the work is
-// balanced to within a few rows.
+// Fused CDBM time step on one grid: one launch per step, each block
+// streaming down strips of the grid (step_fused.hpp, step_wide.hpp).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "launch.hpp"
-#include "step_fused.hpp"
+#include "step_wide.hpp"
 
 namespace cdbm {
 
 namespace {
 
+// pieces > 0: block b takes strip b % nstrips and the (b / nstrips)-th of
+// `pieces` equal row ranges, so that blocks on neighbouring strips stream the
+// same rows at the same time (their row segments share DRAM pages).
+// pieces == 0: block b takes the b-th of gridDim.x equal, contiguous pieces of
+// the strip-major sequence of (strip, row) pairs.
 template <typename S, bool VEC>
-__global__ void __launch_bounds__(FusedGeom<S>::NT) k_step_fused(const S* __restrict__ fin,
-                                                                 S* __restrict__ fout,
-                                                                 const KParams* __restrict__ Kd) {
-    __shared__ __attribute__((aligned(16))) S F0[FusedGeom<S>::F0_ELEMS];
-    __shared__ __attribute__((aligned(16))) S F1[FusedGeom<S>::F1_ELEMS];
+__global__ void __launch_bounds__(StripKernel<S>::NT) k_step_fused(const S* __restrict__ fin,
+                                                                   S* __restrict__ fout,
+                                                                   const KParams* __restrict__ Kd,
+                                                                   int pieces) {
+    using SK = StripKernel<S>;
+    __shared__ __attribute__((aligned(16))) S F0[SK::F0_ELEMS];
+    __shared__ __attribute__((aligned(16))) S F1[SK::F1_ELEMS];
     const KParams& K = *Kd;
-    const int nstrips = (K.nx + FUSED_TX - 1) / FUSED_TX;
-    // Block b takes the b-th of gridDim.x equal, contiguous pieces of the
-    // strip-major sequence of (strip, row) pairs.
-    const int64_t work = (int64_t)nstrips * K.ny;
-    const int64_t u1 = work * (blockIdx.x + 1) / gridDim.x;
-    int64_t u = work * blockIdx.x / gridDim.x;
+    const int nstrips = (K.nx + SK::TX - 1) / SK::TX;
+    // this block's range [u, u1) of the strip-major sequence of (strip, row)
+    int64_t u, u1;
+    if (pieces > 0) {
+        const int s = blockIdx.x % nstrips, p = blockIdx.x / nstrips;
+        const int len = (K.ny + pieces - 1) / pieces;
+        u = (int64_t)s * K.ny + min(K.ny, p * len);
+        u1 = (int64_t)s * K.ny + min(K.ny, (p + 1) * len);
+    } else {
+        const int64_t work = (int64_t)nstrips * K.ny;
+        u = work * blockIdx.x / gridDim.x;
+        u1 = work * (blockIdx.x + 1) / gridDim.x;
+    }
     while (u < u1) {
         const int s = (int)(u / K.ny);
         const int ya = (int)(u - (int64_t)s * K.ny);
         const int yb = (int)min((int64_t)K.ny, (int64_t)ya + (u1 - u));
-        fused_strip<S, VEC>(fin, fout, K, s * FUSED_TX, ya, yb, F0, F1);
+        SK::template run<VEC>(fin, fout, K, s * SK::TX, ya, yb, F0, F1);
         u += yb - ya;
     }
 }
 
+struct Launch {
+    int blocks, pieces;
+};
+
+// Grid of the step.  FP32 uses row-aligned pieces when they keep at least
+// 90 % of the compute units busy; otherwise (and for FP64) a persistent grid
+// with one block per compute unit takes contiguous pieces of the work.
 template <typename S>
-int fused_grid_blocks(const KParams& K) {
-    static int per_cu = -1, cus = -1;
-    if (per_cu < 0) {
+Launch fused_launch(const KParams& K) {
+    static int cus = -1;
+    if (cus < 0) {
         int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess) return 256;
         hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
-        cus = prop.multiProcessorCount;
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step_fused<S, true>, FusedGeom<S>::NT, 0) !=
-                hipSuccess ||
-            nb < 1)
-            nb = 1;
-        per_cu = nb;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+            return Launch{256, 0};
+        cus = prop.multiProcessorCount;   // one block per compute unit (LDS-bound)
     }
-    const int nstrips = (K.nx + FUSED_TX - 1) / FUSED_TX;
+    constexpr int TX = StripKernel<S>::TX;
+    const int nstrips = (K.nx + TX - 1) / TX;
+    if (sizeof(S) == 4) {
+        // rows per piece stay >= 32 so that the pipeline warm-up stays small
+        const int p = std::max(1, std::min(cus / std::max(nstrips, 1), K.ny / 32));
+        if ((int64_t)nstrips * p * 10 >= (int64_t)cus * 9 || nstrips >= cus)
+            return Launch{nstrips * p, p};
+    }
     const int64_t work = (int64_t)nstrips * K.ny;
-    int64_t g = (int64_t)per_cu * cus;
-    // each block should stream at least ~32 rows so the pipeline warm-up stays small
+    int64_t g = cus;
     const int64_t cap = (work + 31) / 32;
     if (g > cap) g = cap;
-    return (int)(g < 1 ? 1 : g);
+    return Launch{(int)(g < 1 ? 1 : g), 0};
 }
 
 }  // namespace
@@ -63,13 +84,13 @@ int fused_grid_blocks(const KParams& K) {
 template <typename S>
 hipError_t launch_step_fused(const void* fin, void* fout, const KParams& K, const KParams* Kd,
                              hipStream_t st) {
-    const int g = fused_grid_blocks<S>(K);
-    if (fused_chunked<S>(K.nx, fin, fout))
-        hipLaunchKernelGGL((k_step_fused<S, true>), dim3(g), dim3(FusedGeom<S>::NT), 0, st,
-                           (const S*)fin, (S*)fout, Kd);
+    const Launch l = fused_launch<S>(K);
+    if (fused_chunked<S>(K.nx, K.ny, fin, fout))
+        hipLaunchKernelGGL((k_step_fused<S, true>), dim3(l.blocks), dim3(StripKernel<S>::NT), 0, st,
+                           (const S*)fin, (S*)fout, Kd, l.pieces);
     else
-        hipLaunchKernelGGL((k_step_fused<S, false>), dim3(g), dim3(FusedGeom<S>::NT), 0, st,
-                           (const S*)fin, (S*)fout, Kd);
+        hipLaunchKernelGGL((k_step_fused<S, false>), dim3(l.blocks), dim3(StripKernel<S>::NT), 0,
+                           st, (const S*)fin, (S*)fout, Kd, l.pieces);
     return hipGetLastError();
 }
 

@@ -55,9 +55,11 @@ hipError_t launch_accumulate_scalar(const double* part, int nblocks, double scal
 // sums of the grids' strip-row counts, ngrids + 1 entries (device).
 template <typename S>
 int batch_blocks();
-template <typename S>
+// Output columns per strip of the fused step for a precision form.
+int strip_width(int precision);
 // chunked: every grid's width and element offset is a multiple of the
 // 16-byte chunk (the buffers' alignment is checked at launch).
+template <typename S>
 hipError_t launch_batch_step(const void* fin, void* fout, const KParams* Ks, const int64_t* f_off,
                              const int64_t* work_start, int ngrids, int nblocks, bool chunked,
                              hipStream_t st);

@@ -170,10 +170,13 @@ constexpr int fused_chunk_elems() {
 inline bool aligned16(const void* a, const void* b) {
     return (((uintptr_t)a | (uintptr_t)b) & 15) == 0;
 }
-// Can a grid of width nx between these buffers use the chunked form?
+// Can a grid of nx * ny cells between these buffers use the chunked form?
+// Besides the chunk geometry, the whole f buffer must be addressable with
+// 32-bit byte offsets from a row start.
 template <typename S>
-inline bool fused_chunked(int nx, const void* fin, const void* fout) {
-    return nx % fused_chunk_elems<S>() == 0 && aligned16(fin, fout);
+inline bool fused_chunked(int nx, int ny, const void* fin, const void* fout) {
+    return nx % fused_chunk_elems<S>() == 0 && aligned16(fin, fout) &&
+           (uint64_t)NV * (uint64_t)nx * (uint64_t)ny * sizeof(S) <= (uint64_t(1) << 32);
 }
 
 // Advance rows [ya, yb) of the strip starting at column x0 of one grid.
@@ -181,9 +184,10 @@ inline bool fused_chunked(int nx, const void* fin, const void* fout) {
 //
 // VEC = false: every lane moves one column of each row (any grid).
 // VEC = true: rows move between HBM and LDS in 16-byte chunks spread over
-// the lanes of the wave; needs nx to be a multiple of the chunk width and
-// 16-byte aligned buffers (fused_chunked), so that every chunk of loaded
-// columns lies inside one row.  A chunk left or right of the grid takes its
+// the lanes of the wave; needs nx to be a multiple of the chunk width,
+// 16-byte aligned buffers and 32-bit offsets (fused_chunked), so that every
+// chunk of loaded columns lies inside one row.  Each lane keeps the byte
+// offsets of its chunks from a row start for the whole strip.  A chunk left or right of the grid takes its
 // periodic image; on a zero-gradient side those ghost columns are never read,
 // because both stages redirect ghost-column reads to the edge column.  The
 // stage-2 result of a row is first written to the F0 slot of that row, which
@@ -215,16 +219,34 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
 
     // Chunk c = k * 64 + lane of a row: velocity c / per_row, chunk c % per_row.
     // Lanes past the last chunk repeat it (the same value to the same place).
-    // With FP32 storage, z is an opaque zero, so the indices are recomputed
-    // at each use instead of being held in registers through the stages
-    // (FP64 runs one wave per SIMD and has the registers to keep them).
-    auto chunk = [&](int k, int per_row, int z, int& i, int& j) {
-        const int c = min(k * 64 + lane + z, NV * per_row - 1);
-        i = c / per_row;
-        j = c - i * per_row;
-    };
-    // strips whose loaded columns reach past a side of the grid
-    const bool edge = x0 < 4 || x0 + FUSED_W0 - 4 > nx;
+    // ld_off / st_off: byte offsets of the chunks this lane loads / stores,
+    // from the start of a row of velocity 0; st_lds: element offset of a
+    // stored chunk in a staged row.  A loaded chunk left or right of the grid
+    // takes its periodic image.
+    uint32_t ld_off[VEC ? NLD : 1], st_off[VEC ? NST : 1];
+    int st_lds[VEC ? NST : 1];
+    uint32_t st_ok = 0;   // bit k: chunk k of the stores lies inside the grid
+    if constexpr (VEC) {
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int c = min(k * 64 + lane, NV * LCH - 1);
+            const int i = c / LCH, j = c - i * LCH;
+            int cs = x0 - 4 + j * CW;
+            if (cs < 0 || cs >= nx) {
+                cs %= nx;
+                if (cs < 0) cs += nx;
+            }
+            ld_off[k] = (uint32_t)(((int64_t)i * cells + cs) * (int64_t)sizeof(S));
+        }
+#pragma unroll
+        for (int k = 0; k < NST; ++k) {
+            const int c = min(k * 64 + lane, NV * SCH - 1);
+            const int i = c / SCH, j = c - i * SCH;
+            st_off[k] = (uint32_t)(((int64_t)i * cells + x0 + j * CW) * (int64_t)sizeof(S));
+            st_lds[k] = i * FUSED_W0 + j * CW;
+            if (x0 + j * CW < nx) st_ok |= 1u << k;
+        }
+    }
 
     // wave w loads row 4 + (t-2)R + w (all 16 velocities) at iteration t;
     // only rows -4 .. nrows+3 are needed
@@ -242,18 +264,9 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
         if (!wanted(q)) return;
         const S* src = fin + (int64_t)source_row(ya + q, ny, bcy) * nx;
         if constexpr (VEC) {
-            const int z = sizeof(S) == 4 ? opaque_zero() : 0;
+            const char* base = (const char*)src;
 #pragma unroll
-            for (int k = 0; k < NLD; ++k) {
-                int i, j;
-                chunk(k, LCH, z, i, j);
-                int cs = x0 - 4 + j * CW;
-                if (edge) {
-                    cs %= nx;
-                    if (cs < 0) cs += nx;
-                }
-                pre[k] = *(const V*)(src + (int64_t)i * cells + cs);
-            }
+            for (int k = 0; k < NLD; ++k) pre[k] = *(const V*)(base + ld_off[k]);
         } else {
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
@@ -336,16 +349,10 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-                S* dst = fout + (int64_t)r2 * nx + x0;
-                const int z = sizeof(S) == 4 ? opaque_zero() : 0;
+                char* dst = (char*)(fout + (int64_t)r2 * nx);
 #pragma unroll
-                for (int k = 0; k < NST; ++k) {
-                    int i, j;
-                    chunk(k, SCH, z, i, j);
-                    if (x0 + j * CW < nx)
-                        *(V*)(dst + (int64_t)i * cells + j * CW) =
-                            *(const V*)(row + i * FUSED_W0 + j * CW);
-                }
+                for (int k = 0; k < NST; ++k)
+                    if (st_ok & (1u << k)) *(V*)(dst + st_off[k]) = *(const V*)(row + st_lds[k]);
             } else if (lane < FUSED_TX && x < nx) {
                 S* dst = fout + (int64_t)r2 * nx + x;
 #pragma unroll
