@@ -26,7 +26,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_fused_mixed_4096_traffic.json")
-KERNEL_SOURCES = ["cell.hpp", "step_fused.hpp", "kernels_step.hip"]
+KERNEL_SOURCES = ["cell.hpp", "step_fused.hpp", "step_wide.hpp", "kernels_step.hip"]
+KERNEL_NAME = "k_step_fused<float, true>"     # the chunked FP32 step the headline times
+COPY_BYTES = 1 << 30                          # the --calibrate-copy kernel moves 1 GiB
 
 
 def kernel_digest() -> str:
@@ -54,7 +56,50 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (3 times), the reference "
                          "kernel for scaling HBM byte counters")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU work: read the counter_collection.csv files of two rocprofv3 "
+                         "--pmc runs (FETCH_SIZE, then WRITE_SIZE) of a --calibrate-copy bench, "
+                         "scale each counter by the plain copy's reading and record the fused "
+                         "step's HBM bytes per launch for the roofline's traffic field")
     return ap.parse_args()
+
+
+def counter_means(csv_path, counter):
+    """Per-dispatch mean of one counter (KiB) for the fused step and for the
+    1 GiB copy kernel of --calibrate-copy."""
+    import csv
+    step, copy = [], []
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Counter_Name") != counter:
+                continue
+            name, v = r["Kernel_Name"], float(r["Counter_Value"])
+            if KERNEL_NAME in name:
+                step.append(v)
+            elif "copy" in name.lower() and int(r.get("Grid_Size", "0") or 0) >= 65536:
+                copy.append(v)
+    if not step or not copy:
+        raise SystemExit(f"{csv_path}: no {counter} rows for {KERNEL_NAME} and the 1 GiB copy")
+    return sum(step) / len(step), sum(copy) / len(copy), len(step)
+
+
+def record_traffic(fetch_csv, write_csv, workload):
+    """HBM bytes per launch of the fused step from FETCH_SIZE and WRITE_SIZE,
+    each scaled so that the plain 1 GiB copy reads / writes 1 GiB."""
+    f_step, f_copy, n_f = counter_means(fetch_csv, "FETCH_SIZE")
+    w_step, w_copy, n_w = counter_means(write_csv, "WRITE_SIZE")
+    f_scale = COPY_BYTES / (f_copy * 1024)
+    w_scale = COPY_BYTES / (w_copy * 1024)
+    rd = f_step * 1024 * f_scale
+    wr = w_step * 1024 * w_scale
+    rec = {"kernel": KERNEL_NAME, "kernel_digest": kernel_digest(), "workload": workload,
+           "bytes_per_launch": rd + wr, "read_bytes": rd, "write_bytes": wr,
+           "fetch_kib_raw": f_step, "write_kib_raw": w_step,
+           "copy_fetch_kib_raw": f_copy, "copy_write_kib_raw": w_copy,
+           "fetch_scale": f_scale, "write_scale": w_scale, "dispatches": [n_f, n_w]}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
 
 
 def time_steps(solver, f_a, f_b, steps, warmup):
@@ -125,6 +170,10 @@ def run_full_seed(run):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        import workloads as W
+        record_traffic(*args.traffic_from, W.headline(seed=args.seed, n=args.n).name)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is described, not built", file=sys.stderr)
@@ -174,7 +223,7 @@ def main():
                    "precision": "mixed"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_step_fused<float>", "alg_bytes_per_launch": alg_bytes,
+                     "kernel": KERNEL_NAME, "alg_bytes_per_launch": alg_bytes,
                      "kernel_digest": digest},
         "wall_s_timed": wall,
     })
