@@ -17,7 +17,10 @@ Readings taken where the text is silent or garbled:
   v dF/dr = [H(r + 1/2) - H(r - 1/2)] / dr.
 * The two-stage Runge-Kutta step is Heun's (SSP) form,
   f1 = f + dt L(f),  f^{n+1} = f/2 + (f1 + dt L(f1)) / 2,
-  with the equilibrium re-evaluated at each stage.
+  with the equilibrium re-evaluated at each stage.  Parity unpinned for this
+  choice: the paper does not say which two-stage form it uses; what every
+  second-order two-stage form shares (the amplification 1 - z + z^2/2 of a
+  uniform relaxation) is pinned, Heun against the midpoint form is not.
 * Two ghost layers per side are refreshed before every stage: periodic wrap
   or a zero-gradient copy of the edge cell.
 """
