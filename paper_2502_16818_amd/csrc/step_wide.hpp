@@ -9,7 +9,10 @@
 // per velocity), twice the length of the 60-column strip's segments, and
 // stage 1 is recomputed on the same 4 halo columns for twice the outputs.
 // Wave (r, h) of a row r handles columns [64h, 64h + 64) of the strip's
-// stage-1 and stage-2 windows.
+// stage-1 and stage-2 windows.  The global loads of the next rows are issued
+// in two halves, before stage 1 and before stage 2, and each lane stores its
+// own stage-2 cell: spreading the memory instructions over the iteration
+// keeps waves from stalling on a full memory queue.
 #pragma once
 
 #include "step_fused.hpp"
@@ -43,7 +46,6 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
     constexpr int CW = 4;
     constexpr int LCH = W0 / CW;                  // 32 chunks per loaded velocity row
     constexpr int NLD = NV * LCH / (64 * G::WPR); // 4 chunk loads per lane and row
-    constexpr int NST = NV / 4;                   // chunk stores per lane and row
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -61,14 +63,8 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
     // c = 256h + 64k + lane, k < NLD, which land at element 4c of the row's F0
     // slot.  Their velocity is 8h + 2k + (lane >> 5) and their column does not
     // depend on k, so one per-lane byte offset ld_lane serves all of them.
-    // Stores: wave half h writes its own stage-2 columns 64h + 4j, j < 16, of
-    // velocity 4k + (lane >> 4) with j = lane & 15 (chunks past the strip or
-    // the grid are skipped); st_lane and st_lds are the per-lane parts of
-    // their global byte offset and staged element offset.
     const uint32_t plane = (uint32_t)(cells * (int64_t)sizeof(S));   // bytes per velocity plane
-    uint32_t ld_lane = 0, st_lane = 0;
-    int st_lds = 0;
-    bool st_ok = false;
+    uint32_t ld_lane = 0;
     if constexpr (VEC) {
         int cs = x0 - 4 + 4 * (lane & 31);
         if (cs < 0 || cs >= nx) {   // periodic image (zero-gradient ghosts are never read)
@@ -76,10 +72,6 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
             if (cs < 0) cs += nx;
         }
         ld_lane = (uint32_t)(lane >> 5) * plane + (uint32_t)cs * (uint32_t)sizeof(S);
-        const int cl = 64 * h + 4 * (lane & 15);    // strip column of the stored chunk
-        st_lane = (uint32_t)(lane >> 4) * plane + (uint32_t)(x0 + cl) * (uint32_t)sizeof(S);
-        st_lds = (lane >> 4) * W0 + 4 + cl;
-        st_ok = cl < TX && x0 + cl < nx;
     }
     // per-column form: global column this lane loads
     const int gc = VEC ? 0 : map_index(x0 - 4 + col, nx, bcx);
@@ -90,7 +82,8 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
     P pre[NPRE];
     auto load_row = [&](int t) { return 4 + (t - 2) * R + rw; };
     auto wanted = [&](int q) { return q >= -4 && q < nrows + 4; };
-    auto issue_loads = [&](int t) {
+    // loads of part `half` (0 or 1) of the row of iteration t
+    auto issue_loads = [&](int t, int half) {
         const int q = load_row(t);
         if (!wanted(q)) return;
         const S* src = fin + (int64_t)source_row(ya + q, ny, bcy) * nx;
@@ -98,10 +91,12 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
             const char* base = (const char*)src;
 #pragma unroll
             for (int k = 0; k < NLD; ++k)
-                pre[k] = *(const V*)(base + (uint32_t)(8 * h + 2 * k) * plane + ld_lane);
+                if (k / (NLD / 2) == half)
+                    pre[k] = *(const V*)(base + (uint32_t)(8 * h + 2 * k) * plane + ld_lane);
         } else {
 #pragma unroll
-            for (int i = 0; i < NV; ++i) pre[i] = src[(int64_t)i * cells + gc];
+            for (int i = 0; i < NV; ++i)
+                if (i / (NV / 2) == half) pre[i] = src[(int64_t)i * cells + gc];
         }
     };
     // called at iteration t, for the rows of that iteration
@@ -120,11 +115,12 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
 
     const int t0 = 2 - (8 + R - 1) / R;          // first iteration whose loads reach row -4
     const int t_end = (nrows + R - 1) / R + 1;   // last iteration with a stage-2 row
-    issue_loads(t0);
+    issue_loads(t0, 0);
+    issue_loads(t0, 1);
     for (int t = t0; t <= t_end; ++t) {
         lds_barrier();   // the stages of iteration t-1 are done with the slots reused below
         store_loads(t);
-        if (t < t_end) issue_loads(t + 1);
+        if (t < t_end) issue_loads(t + 1, 0);
         lds_barrier();
 
         // stage 1: f^(1) at row q1, column x0 - 2 + col
@@ -150,6 +146,7 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
         }
         lds_barrier();
 
+        if (t < t_end) issue_loads(t + 1, 1);
         // stage 2: f^{n+1} at row q2, column x0 + col
         const int q2 = (t - 2) * R + rw;
         if (q2 >= 0 && q2 < nrows) {
@@ -166,31 +163,11 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
             }
             S out[NV];
             stage_cell_k<S, true>(ld, K, out);
-            S* row = F0 + slot(q2) * NV * W0 + 4;   // f^n of row q2 from column x0
-            if constexpr (VEC) {
-                // each lane reads and then overwrites only its own column here
-                if (col < TX) {
-#pragma unroll
-                    for (int i = 0; i < NV; ++i)
-                        row[i * W0 + col] = fma(S(0.5), row[i * W0 + col], out[i]);
-                }
-                // the chunks below gather columns written by other lanes of this wave
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-                const S* stg = F0 + slot(q2) * NV * W0;
-                char* dst = (char*)(fout + (int64_t)r2 * nx);
-                if (st_ok) {
-#pragma unroll
-                    for (int k = 0; k < NST; ++k)
-                        *(V*)(dst + (uint32_t)(4 * k) * plane + st_lane) =
-                            *(const V*)(stg + 4 * k * W0 + st_lds);
-                }
-            } else if (col < TX && x < nx) {
+            if (col < TX && x < nx) {
+                const S* fn = F0 + slot(q2) * NV * W0 + 4 + col;   // f^n of the cell
                 S* dst = fout + (int64_t)r2 * nx + x;
 #pragma unroll
-                for (int i = 0; i < NV; ++i)
-                    dst[(int64_t)i * cells] = fma(S(0.5), row[i * W0 + col], out[i]);
+                for (int i = 0; i < NV; ++i) dst[(int64_t)i * cells] = fma(S(0.5), fn[i * W0], out[i]);
             }
         }
     }
