@@ -13,8 +13,9 @@
 // Each stage runs just two rows behind what it needs, so R + 4 rows of each
 // ring are live at once; each f value crosses HBM once in and once out per
 // step, and stage 1 is recomputed only on the 2-column x halo (64 columns
-// for 60 outputs).  The global loads of iteration t+1 are issued before the
-// stages of iteration t.
+// for 60 outputs).  The global loads of iteration t+1 are issued during
+// iteration t, in two halves: before stage 1 and before stage 2.  This strip
+// serves FP64 storage; FP32 storage uses the wider strip of step_wide.hpp.
 //
 // Boundary conditions: f^n ghost cells are loaded through the periodic wrap
 // or the edge clamp, which is exactly the ghost fill of the scheme.  For a
@@ -36,9 +37,9 @@ constexpr int FUSED_W0 = FUSED_TX + 8;     // F0 row width
 constexpr int FUSED_W1 = FUSED_TX + 4;     // F1 row width (= 64 = one wave)
 
 // Rows per iteration: one wave per row.  The ring depth R + 4 must be a
-// power of two.  FP32 uses 12 (768 threads, 132 KB of LDS, one block per
-// compute unit, three waves per SIMD); FP64 needs twice the LDS per row and
-// uses 4.
+// power of two.  With FP64 storage, 4 rows (256 threads, 132 KB of LDS, one
+// block per compute unit); 12 rows would fit FP32 storage (132 KB, three
+// waves per SIMD), which the wide strip of step_wide.hpp serves instead.
 template <typename S>
 struct FusedRows;
 template <>
@@ -187,12 +188,11 @@ inline bool fused_chunked(int nx, int ny, const void* fin, const void* fout) {
 // the lanes of the wave; needs nx to be a multiple of the chunk width,
 // 16-byte aligned buffers and 32-bit offsets (fused_chunked), so that every
 // chunk of loaded columns lies inside one row.  Each lane keeps the byte
-// offsets of its chunks from a row start for the whole strip.  A chunk left or right of the grid takes its
-// periodic image; on a zero-gradient side those ghost columns are never read,
-// because both stages redirect ghost-column reads to the edge column.  The
-// stage-2 result of a row is first written to the F0 slot of that row, which
-// no other wave reads before its refill behind the next barrier, and is
-// stored from there in chunks.
+// offsets of its chunks from a row start for the whole strip.  A chunk left
+// or right of the grid takes its periodic image; on a zero-gradient side
+// those ghost columns are never read, because both stages redirect
+// ghost-column reads to the edge column.  Every lane stores its own stage-2
+// cell.
 template <typename S, bool VEC>
 __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __restrict__ fout,
                                             const KParams& K, int x0, int ya, int yb, S* F0,
@@ -204,8 +204,6 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
     constexpr int CW = 16 / (int)sizeof(S);        // elements per chunk
     constexpr int LCH = FUSED_W0 / CW;             // chunks per loaded velocity row
     constexpr int NLD = (NV * LCH + 63) / 64;      // chunk loads per lane and row
-    constexpr int SCH = FUSED_TX / CW;             // chunks per stored velocity row
-    constexpr int NST = (NV * SCH + 63) / 64;      // chunk stores per lane and row
     static_assert(FUSED_W0 % CW == 0 && FUSED_TX % CW == 0 && 4 % CW == 0, "chunk geometry");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -219,13 +217,10 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
 
     // Chunk c = k * 64 + lane of a row: velocity c / per_row, chunk c % per_row.
     // Lanes past the last chunk repeat it (the same value to the same place).
-    // ld_off / st_off: byte offsets of the chunks this lane loads / stores,
-    // from the start of a row of velocity 0; st_lds: element offset of a
-    // stored chunk in a staged row.  A loaded chunk left or right of the grid
-    // takes its periodic image.
-    uint32_t ld_off[VEC ? NLD : 1], st_off[VEC ? NST : 1];
-    int st_lds[VEC ? NST : 1];
-    uint32_t st_ok = 0;   // bit k: chunk k of the stores lies inside the grid
+    // ld_off: byte offsets of the chunks this lane loads, from the start of a
+    // row of velocity 0.  A chunk left or right of the grid takes its
+    // periodic image.
+    uint32_t ld_off[VEC ? NLD : 1];
     if constexpr (VEC) {
 #pragma unroll
         for (int k = 0; k < NLD; ++k) {
@@ -237,14 +232,6 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
                 if (cs < 0) cs += nx;
             }
             ld_off[k] = (uint32_t)(((int64_t)i * cells + cs) * (int64_t)sizeof(S));
-        }
-#pragma unroll
-        for (int k = 0; k < NST; ++k) {
-            const int c = min(k * 64 + lane, NV * SCH - 1);
-            const int i = c / SCH, j = c - i * SCH;
-            st_off[k] = (uint32_t)(((int64_t)i * cells + x0 + j * CW) * (int64_t)sizeof(S));
-            st_lds[k] = i * FUSED_W0 + j * CW;
-            if (x0 + j * CW < nx) st_ok |= 1u << k;
         }
     }
 
@@ -259,17 +246,20 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
     const int gc_b = VEC ? 0 : map_index(x0 - 4 + 64 + (lane & 3), nx, bcx);
     auto load_row = [&](int t) { return 4 + (t - 2) * R + wave; };
     auto wanted = [&](int q) { return q >= -4 && q < nrows + 4; };
-    auto issue_loads = [&](int t) {
+    // loads of part `half` (0 or 1) of the row of iteration t
+    auto issue_loads = [&](int t, int half) {
         const int q = load_row(t);
         if (!wanted(q)) return;
         const S* src = fin + (int64_t)source_row(ya + q, ny, bcy) * nx;
         if constexpr (VEC) {
             const char* base = (const char*)src;
 #pragma unroll
-            for (int k = 0; k < NLD; ++k) pre[k] = *(const V*)(base + ld_off[k]);
+            for (int k = 0; k < NLD; ++k)
+                if ((k < (NLD + 1) / 2 ? 0 : 1) == half) pre[k] = *(const V*)(base + ld_off[k]);
         } else {
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
+                if ((i < NV / 2 ? 0 : 1) != half) continue;
                 pre[i] = src[(int64_t)i * cells + gc_a];
                 pre[NV + i] = (lane < 4) ? src[(int64_t)i * cells + gc_b] : S(0);
             }
@@ -296,11 +286,12 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
     // first iteration whose loads reach row -4; stage 2 finishes at t_end
     const int t0 = 2 - (8 + R - 1) / R;
     const int t_end = (nrows + R - 1) / R + 1;
-    issue_loads(t0);
+    issue_loads(t0, 0);
+    issue_loads(t0, 1);
     for (int t = t0; t <= t_end; ++t) {
         lds_barrier();   // the stages of iteration t-1 are done with the slots reused below
         store_loads(t);
-        if (t < t_end) issue_loads(t + 1);
+        if (t < t_end) issue_loads(t + 1, 0);
         lds_barrier();
 
         // stage 1: f^(1) at row q1, column x0 - 2 + lane
@@ -323,6 +314,7 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
         }
         lds_barrier();
 
+        if (t < t_end) issue_loads(t + 1, 1);
         // stage 2: f^{n+1} at row q2, column x0 + lane
         const int q2 = (t - 2) * R + wave;
         if (q2 >= 0 && q2 < nrows) {
@@ -339,25 +331,11 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
             }
             S out[NV];
             stage_cell_k<S, true>(ld, K, out);
-            S* row = F0 + slot(q2) * NV * FUSED_W0 + 4;   // f^n of row q2 from column x0
-            if constexpr (VEC) {
-                // each lane reads and then overwrites only its own column here
-#pragma unroll
-                for (int i = 0; i < NV; ++i)
-                    row[i * FUSED_W0 + lane] = fma(S(0.5), row[i * FUSED_W0 + lane], out[i]);
-                // the chunks below gather columns written by other lanes
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-                char* dst = (char*)(fout + (int64_t)r2 * nx);
-#pragma unroll
-                for (int k = 0; k < NST; ++k)
-                    if (st_ok & (1u << k)) *(V*)(dst + st_off[k]) = *(const V*)(row + st_lds[k]);
-            } else if (lane < FUSED_TX && x < nx) {
+            if (lane < FUSED_TX && x < nx) {
+                const S* fn = F0 + slot(q2) * NV * FUSED_W0 + 4 + lane;   // f^n of the cell
                 S* dst = fout + (int64_t)r2 * nx + x;
 #pragma unroll
-                for (int i = 0; i < NV; ++i)
-                    dst[(int64_t)i * cells] = fma(S(0.5), row[i * FUSED_W0 + lane], out[i]);
+                for (int i = 0; i < NV; ++i) dst[(int64_t)i * cells] = fma(S(0.5), fn[i * FUSED_W0], out[i]);
             }
         }
     }
