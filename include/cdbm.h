@@ -54,6 +54,7 @@ enum {
 
 enum { CDBM_PERIODIC = 0, CDBM_ZERO_GRADIENT = 1 };
 enum { CDBM_FP64 = 0, CDBM_MIXED = 1 };
+enum { CDBM_STEP_AUTO = 0, CDBM_STEP_FUSED = 1, CDBM_STEP_SPLIT = 2 };
 
 /* Run parameters (Secs. 2 and 3).
  *   nx, ny      grid cells (ny = 1 for a tube); 1 <= nx, ny <= 65536 and
@@ -70,7 +71,16 @@ enum { CDBM_FP64 = 0, CDBM_MIXED = 1 };
  *               side copied from the edge cell before each stage).
  *   precision   CDBM_FP64: f stored and advected in double.  CDBM_MIXED: f
  *               stored and advected in float; moments, equilibrium and the
- *               relaxation difference f - f^eq in double. */
+ *               relaxation difference f - f^eq in double.
+ *   step_form   how cdbm_step runs a time step; all forms give the same
+ *               result up to rounding order.  CDBM_STEP_FUSED: both stages
+ *               in one launch that streams strips of the grid through LDS
+ *               (f crosses HBM once in and once out per step).
+ *               CDBM_STEP_SPLIT: two single-stage launches, one cell per
+ *               thread, f^(1) through a handle-owned buffer (faster on small
+ *               grids, where the fused launch has too few strips to fill the
+ *               chip).  CDBM_STEP_AUTO: split up to 512 x 512 cells, fused
+ *               above.  Ignored by the batched form (always fused). */
 typedef struct cdbm_params {
     int32_t nx, ny;
     double dx, dy, dt, tau;
@@ -79,6 +89,7 @@ typedef struct cdbm_params {
     double eta[4];
     int32_t bc_x, bc_y;
     int32_t precision;
+    int32_t step_form;
 } cdbm_params;
 
 typedef struct cdbm_handle cdbm_handle;

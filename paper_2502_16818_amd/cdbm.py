@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libcdbm.so")
 OK, EINVAL, ESINGULAR, ENONPHYS, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5
 PERIODIC, ZERO_GRADIENT = 0, 1
 FP64, MIXED = 0, 1
+STEP_AUTO, STEP_FUSED, STEP_SPLIT = 0, 1, 2
 
 EXPORTS = (
     "cdbm_last_error", "cdbm_create", "cdbm_destroy", "cdbm_get_params", "cdbm_init",
@@ -41,6 +42,7 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("gamma", ctypes.c_double),
         ("v", ctypes.c_double * 4), ("eta", ctypes.c_double * 4),
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("step_form", ctypes.c_int32),
     ]
 
 
@@ -110,7 +112,7 @@ def gamma_to_extra_dof(gamma: float) -> float:
 
 
 def make_params(nx, ny, dx, dy, dt, tau, gamma, v, eta, bc_x=PERIODIC, bc_y=PERIODIC,
-                precision=FP64) -> Params:
+                precision=FP64, step_form=0) -> Params:
     p = Params()
     p.nx, p.ny = int(nx), int(ny)
     p.dx, p.dy, p.dt, p.tau, p.gamma = float(dx), float(dy), float(dt), float(tau), float(gamma)
@@ -118,6 +120,7 @@ def make_params(nx, ny, dx, dy, dt, tau, gamma, v, eta, bc_x=PERIODIC, bc_y=PERI
         p.v[k] = float(v[k])
         p.eta[k] = float(eta[k])
     p.bc_x, p.bc_y, p.precision = int(bc_x), int(bc_y), int(precision)
+    p.step_form = int(step_form)
     return p
 
 
@@ -136,9 +139,9 @@ class Solver:
         self.dtype = torch.float32 if params.precision == MIXED else torch.float64
 
     @classmethod
-    def from_run(cls, run, precision=FP64) -> "Solver":
+    def from_run(cls, run, precision=FP64, step_form=0) -> "Solver":
         return cls(make_params(run.nx, run.ny, run.dx, run.dy, run.dt, run.tau, run.gamma, run.v,
-                               run.eta, run.bc_x, run.bc_y, precision))
+                               run.eta, run.bc_x, run.bc_y, precision, step_form))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

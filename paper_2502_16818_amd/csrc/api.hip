@@ -132,7 +132,20 @@ int run_steps(StepFn fn, const void* ctx, const void* fin, void* fout, void* scr
 
 namespace {
 
+// With CDBM_STEP_AUTO, grids of up to this many cells take the step as two
+// single-stage launches (f^(1) through the handle's stage buffer): one cell
+// per thread fills the chip, where the fused step has too few strip pieces
+// to hide its latency.
+constexpr int64_t SPLIT_STEP_CELLS = int64_t(1) << 18;   // 512 x 512
+
 hipError_t step_once(const cdbm_handle* h, const void* fin, void* fout, hipStream_t st) {
+    if (h->split) {
+        hipError_t e = mixed(h) ? launch_stage<float>(fin, nullptr, h->stage, false, h->k, h->kdev, st)
+                                : launch_stage<double>(fin, nullptr, h->stage, false, h->k, h->kdev, st);
+        if (e != hipSuccess) return e;
+        return mixed(h) ? launch_stage<float>(h->stage, fin, fout, true, h->k, h->kdev, st)
+                        : launch_stage<double>(h->stage, fin, fout, true, h->k, h->kdev, st);
+    }
     return mixed(h) ? launch_step_fused<float>(fin, fout, h->k, h->kdev, st)
                     : launch_step_fused<double>(fin, fout, h->k, h->kdev, st);
 }
@@ -176,7 +189,10 @@ int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
     h->elem = mixed(h) ? sizeof(float) : sizeof(double);
     h->fbytes = (size_t)cdbm::NV * (size_t)h->cells * h->elem;
     const int tau_blocks = ((p->nx + 63) / 64) * ((p->ny + 3) / 4);
+    h->split = p->step_form == CDBM_STEP_SPLIT ||
+               (p->step_form == CDBM_STEP_AUTO && h->cells <= SPLIT_STEP_CELLS);
     if (ensure_buffer(h, &h->scratch) != CDBM_OK ||
+        (h->split && ensure_buffer(h, &h->stage) != CDBM_OK) ||
         hipMalloc(&h->partials, sizeof(double) * 4 * REDUCE_BLOCKS) != hipSuccess ||
         hipMalloc(&h->tau_part, sizeof(double) * tau_blocks) != hipSuccess ||
         hipMalloc(&h->flag, sizeof(int)) != hipSuccess ||

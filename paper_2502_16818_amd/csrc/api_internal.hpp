@@ -38,7 +38,8 @@ struct cdbm_handle {
     size_t elem = 8;
     size_t fbytes = 0;
     void* scratch = nullptr;    // f-sized ping-pong buffer
-    void* stage = nullptr;      // f-sized buffer for the adjoint's stage-1 state
+    void* stage = nullptr;      // f-sized buffer of a stage-1 state (adjoint, split steps)
+    bool split = false;         // step as two single-stage launches (small grids)
     void* lam_mid = nullptr;    // f-sized buffer for the adjoint's intermediate product
     double* partials = nullptr; // reduction partials
     double* tau_part = nullptr; // per-block partial sums of the adjoint's tau term

@@ -126,6 +126,10 @@ int build_params(const cdbm_params& p, KParams& k, std::string& err) {
         err = "precision must be CDBM_FP64 or CDBM_MIXED";
         return CDBM_EINVAL;
     }
+    if (p.step_form < CDBM_STEP_AUTO || p.step_form > CDBM_STEP_SPLIT) {
+        err = "step_form must be CDBM_STEP_AUTO, CDBM_STEP_FUSED or CDBM_STEP_SPLIT";
+        return CDBM_EINVAL;
+    }
 
     // Velocity table, Eqs. (2)-(3).
     double vx[NV], vy[NV], eta[NV];

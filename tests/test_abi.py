@@ -40,6 +40,22 @@ def test_library_exports_every_declared_function(lib):
     assert set(declared_functions()) == set(cdbm.EXPORTS)
 
 
+def test_binding_struct_matches_header():
+    """The ctypes mirror of cdbm_params lists the header's fields in order."""
+    import re
+    from paper_2502_16818_amd import cdbm
+    text = open(HEADER).read()
+    body = re.search(r"typedef struct cdbm_params \{(.*?)\} cdbm_params;", text, re.S).group(1)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for part in decl.split(None, 1)[1].split(","):
+            names.append(part.strip().split("[")[0])
+    assert names == [f[0] for f in cdbm.Params._fields_]
+
+
 def _params(**kw):
     from paper_2502_16818_amd import make_params
     base = dict(nx=16, ny=8, dx=0.1, dy=0.1, dt=1e-4, tau=1e-4, gamma=1.4,
@@ -51,7 +67,8 @@ def _params(**kw):
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(ny=-3), dict(nx=70000), dict(dx=0.0), dict(tau=-1.0),
     dict(dt=3e-4, tau=1e-4), dict(gamma=1.0), dict(gamma=2.5), dict(v=(1.4, 0.0, 1.1, 1.0)),
-    dict(eta=(3.0, -1.0, 0.0, 0.0)), dict(bc_x=7), dict(precision=5),
+    dict(eta=(3.0, -1.0, 0.0, 0.0)), dict(bc_x=7), dict(precision=5), dict(step_form=3),
+    dict(step_form=-1),
 ])
 def test_create_rejects_invalid_parameters(lib, bad):
     p = _params(**bad)

@@ -13,12 +13,14 @@ from helpers import field_errors, oracle_after, oracle_f0, rel_l2, rel_max, to_n
 pytestmark = pytest.mark.gpu
 
 FP64, MIXED = 0, 1   # CDBM_FP64, CDBM_MIXED of include/cdbm.h
+AUTO, FUSED, SPLIT = 0, 1, 2   # CDBM_STEP_* of include/cdbm.h
+FORMS = {"fused": FUSED, "split": SPLIT}
 
 
-def _solver(run, precision):
+def _solver(run, precision, form=AUTO):
     from paper_2502_16818_amd import Solver
-    print(f"[case] {run.name} {run.nx}x{run.ny} precision={precision}", flush=True)
-    return Solver.from_run(run, precision)
+    print(f"[case] {run.name} {run.nx}x{run.ny} precision={precision} step_form={form}", flush=True)
+    return Solver.from_run(run, precision, form)
 
 
 def _cases():
@@ -72,10 +74,11 @@ def test_init_moments_tne_fp64(run):
     assert np.abs(d_gpu - d_ref).max() <= 1e-9 * np.abs(d_ref).max()
 
 
+@pytest.mark.parametrize("form", sorted(FORMS))
 @pytest.mark.parametrize("run", _cases(), ids=lambda r: r.name)
 @pytest.mark.parametrize("nsteps", [1, 2, 5])
-def test_step_fp64_matches_oracle(run, nsteps):
-    s = _solver(run, FP64)
+def test_step_fp64_matches_oracle(run, nsteps, form):
+    s = _solver(run, FP64, FORMS[form])
     f = s.init(run.rho, run.ux, run.uy, run.T)
     out = s.step(f, nsteps=nsteps)
     _, ref = oracle_after(run, nsteps)
@@ -84,9 +87,10 @@ def test_step_fp64_matches_oracle(run, nsteps):
     assert err < 1e-12
 
 
-def test_step_fp64_long_random_run():
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_step_fp64_long_random_run(form):
     run = W.random_periodic(96, 70, seed=3, dt=1e-4, tau=2e-4)
-    s = _solver(run, FP64)
+    s = _solver(run, FP64, FORMS[form])
     f = s.init(run.rho, run.ux, run.uy, run.T)
     out = s.step(f, nsteps=60)       # takes the captured-graph path (>= 32 steps)
     p, ref = oracle_after(run, 60)
@@ -112,9 +116,10 @@ def test_sod_tube_full_run_fp64():
     assert max(errs.values()) < 1e-12
 
 
+@pytest.mark.parametrize("form", sorted(FORMS))
 @pytest.mark.parametrize("run", _cases()[:6] + _chunked_cases(), ids=lambda r: r.name)
-def test_step_mixed_against_fp64_oracle(run):
-    s = _solver(run, MIXED)
+def test_step_mixed_against_fp64_oracle(run, form):
+    s = _solver(run, MIXED, FORMS[form])
     f = s.init(run.rho, run.ux, run.uy, run.T)
     n = 20
     out = s.step(f, nsteps=n)
@@ -126,6 +131,20 @@ def test_step_mixed_against_fp64_oracle(run):
     print(errs)
     assert errs["rho"] < 1e-5 and errs["T"] < 1e-5
     assert errs["ux"] < 1e-4 and errs["uy"] < 1e-4
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_fused_and_split_steps_are_bitwise_equal(precision):
+    """Both step forms evaluate the same per-cell arithmetic in the same order;
+    only where f^(1) lives (LDS or HBM) differs."""
+    for run in [_cases()[2], _cases()[5]] + _chunked_cases()[:3]:
+        outs = []
+        for form in (FUSED, SPLIT):
+            s = _solver(run, precision, form)
+            f = s.init(run.rho, run.ux, run.uy, run.T)
+            outs.append(s.step(f, nsteps=7))
+            s.close()
+        assert torch.equal(outs[0], outs[1]), run.name
 
 
 def test_conserved_totals_periodic_fp64():
