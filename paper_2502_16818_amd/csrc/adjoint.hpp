@@ -131,70 +131,90 @@ __device__ __forceinline__ double moments_vjp_k(const Macro& m, const KParams& K
     return g.rho + (g.ux * cx + g.uy * cy + g.T * (e - a * m.T) / a) / m.rho;
 }
 
-// Accessor of one distribution along one axis of one grid, with the
-// boundary map of the grid applied to extended positions.
+// The transposes run on a tile staged in LDS: one velocity's state and
+// adjoint on a block of ATX x ATY cells plus a halo of AH cells each side
+// (positions mapped through the boundary already: periodic images or
+// zero-gradient copies; the adjoint is zero at zero-gradient ghosts, where
+// no real cell exists).  Positions are local tile indices along one line;
+// the global index of a position only decides which gathers a
+// zero-gradient side skips.
+constexpr int ATX = 64, ATY = 4, AH = 3;
+constexpr int ATW = ATX + 2 * AH, ATH = ATY + 2 * AH;
+
 template <typename S>
-struct Line {
-    const S* __restrict__ base;   // f_i (or a_i) at row/column 0 of the line
-    int stride;                   // element stride between neighbours on the axis
-    int n;                        // cells on the axis
-    int bc;
-    __device__ __forceinline__ int map(int p) const { return wrap_or_clamp(p, n, bc); }
-    __device__ __forceinline__ S at(int p) const { return base[(int64_t)map(p) * stride]; }
+struct TileLine {
+    const S* base;   // tile element of local position 0 on the line
+    int stride;
+    __device__ __forceinline__ S at(int l) const { return base[l * stride]; }
 };
 
-// Face selection at cell x of the distribution on line F.
+// Face selections precomputed per tile position: bit 0 alpha, bit 1 beta of
+// minmod(F(l+1) - F(l), F(l) - F(l-1)) along the line (Eq. (16) branch order).
+struct SelLine {
+    const unsigned char* base;
+    int stride;
+    __device__ __forceinline__ void at(int l, double& al, double& be) const {
+        const int c = base[l * stride];
+        al = (double)(c & 1);
+        be = (double)(c >> 1);
+    }
+};
+
 template <typename S>
-__device__ __forceinline__ void face_sel(const Line<S>& F, int x, double& al, double& be) {
-    const S fm = F.at(x - 1), f0 = F.at(x), fp = F.at(x + 1);
+__device__ __forceinline__ unsigned char face_code(S fm, S f0, S fp) {
+    double al, be;
     minmod_select<S>(fp - f0, f0 - fm, al, be);
+    return (unsigned char)((al != 0.0 ? 1 : 0) | (be != 0.0 ? 2 : 0));
 }
 
-// Gather of the NND transpose at extended position p (see the header).
-// F: the state (selections are taken in its own precision); A: the adjoint.
-template <typename S, bool POS>
-__device__ __forceinline__ double nnd_gather(const Line<S>& F, const Line<double>& A, int p) {
+// Gather of the NND transpose at local position lp, global position gp
+// (see the header), with the selections read from a SelLine.
+template <bool POS>
+__device__ __forceinline__ double nnd_gather(const SelLine& Sl, const TileLine<double>& A, int lp,
+                                             int gp, int n, int bc) {
     double acc = 0.0;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-        const int k = POS ? 1 - kk : 2 - kk;   // POS: +1, 0, -1, -2; else +2, +1, 0, -1
-        int x = p - k;
-        if (F.bc == CDBM_PERIODIC) {
-            x = F.map(x);
-        } else if (x < 0 || x >= F.n) {
-            continue;
-        }
+        const int k = POS ? 1 - kk : 2 - kk;
+        const int gx = gp - k;
+        if (bc != CDBM_PERIODIC && (gx < 0 || gx >= n)) continue;
+        const int l = lp - k;
         double coef;
         if (POS) {
-            double a0, b0, a1, b1;   // s(x-1), s(x)
-            face_sel(F, x - 1, a0, b0);
-            face_sel(F, x, a1, b1);
+            double a0, b0, a1, b1;   // s(l-1), s(l)
+            Sl.at(l - 1, a0, b0);
+            Sl.at(l, a1, b1);
             if (k == 1) coef = 0.5 * a1;
             else if (k == 0) coef = 1.0 + 0.5 * (b1 - a0 - a1);
             else if (k == -1) coef = -1.0 - 0.5 * (b1 - a0 + b0);
             else coef = 0.5 * b0;
         } else {
-            double a1, b1, a2, b2;   // s(x), s(x+1)
-            face_sel(F, x, a1, b1);
-            face_sel(F, x + 1, a2, b2);
+            double a1, b1, a2, b2;   // s(l), s(l+1)
+            Sl.at(l, a1, b1);
+            Sl.at(l + 1, a2, b2);
             if (k == 2) coef = -0.5 * a2;
             else if (k == 1) coef = 1.0 + 0.5 * (a2 - b2 + a1);
             else if (k == 0) coef = -1.0 + 0.5 * (b2 - a1 + b1);
             else coef = -0.5 * b1;
         }
-        acc = fma(coef, A.at(x), acc);
+        acc = fma(coef, A.at(l), acc);
     }
     return acc;
 }
 
-// Full NND transpose at real cell y (ghost aliases folded in).
-template <typename S, bool POS>
-__device__ __forceinline__ double nnd_transpose(const Line<S>& F, const Line<double>& A, int y) {
-    double acc = nnd_gather<S, POS>(F, A, y);
-    if (F.bc == CDBM_ZERO_GRADIENT) {
-        if (y == 0) acc += nnd_gather<S, POS>(F, A, -1) + nnd_gather<S, POS>(F, A, -2);
-        if (y == F.n - 1)
-            acc += nnd_gather<S, POS>(F, A, F.n) + nnd_gather<S, POS>(F, A, F.n + 1);
+// Full NND transpose at the real cell of local position lc, global position
+// gc, with the ghost aliases of a zero-gradient side folded in.
+template <bool POS>
+__device__ __forceinline__ double nnd_transpose(const SelLine& Sl, const TileLine<double>& A,
+                                                int lc, int gc, int n, int bc) {
+    double acc = nnd_gather<POS>(Sl, A, lc, gc, n, bc);
+    if (bc == CDBM_ZERO_GRADIENT) {
+        if (gc == 0)
+            acc += nnd_gather<POS>(Sl, A, lc - 1, -1, n, bc) +
+                   nnd_gather<POS>(Sl, A, lc - 2, -2, n, bc);
+        if (gc == n - 1)
+            acc += nnd_gather<POS>(Sl, A, lc + 1, n, n, bc) +
+                   nnd_gather<POS>(Sl, A, lc + 2, n + 1, n, bc);
     }
     return acc;
 }

@@ -18,10 +18,6 @@
 
 using namespace cdbm;
 
-namespace cdbm {
-int stage_adjoint_blocks(const KParams& K);
-}
-
 namespace {
 
 template <typename S>
@@ -31,12 +27,11 @@ int step_adjoint_impl(cdbm_handle* h, const void* f_n, const void* lam_np1, void
     const int nb = stage_adjoint_blocks(K);
     hipError_t e = launch_stage<S>(f_n, nullptr, h->stage, false, K, h->kdev, st);
     if (e != hipSuccess) return hip_fail(e, "stage recompute launch");
-    e = launch_stage_adjoint<S>(h->stage, lam_np1, nullptr, h->lam_mid, h->tau_part, nb, 0.5, 0.0,
-                                K, st);
+    e = launch_stage_adjoint<S>(h->stage, lam_np1, nullptr, h->lam_mid, h->tau_part, 0.5, 0.0, K, st);
     if (e != hipSuccess) return hip_fail(e, "stage adjoint launch");
     e = launch_accumulate_scalar(h->tau_part, nb, 1.0, dtau, st);
     if (e != hipSuccess) return hip_fail(e, "tau accumulation launch");
-    e = launch_stage_adjoint<S>(f_n, h->lam_mid, lam_np1, lam_n, h->tau_part, nb, 1.0, 0.5, K, st);
+    e = launch_stage_adjoint<S>(f_n, h->lam_mid, lam_np1, lam_n, h->tau_part, 1.0, 0.5, K, st);
     if (e != hipSuccess) return hip_fail(e, "stage adjoint launch");
     e = launch_accumulate_scalar(h->tau_part, nb, 1.0, dtau, st);
     if (e != hipSuccess) return hip_fail(e, "tau accumulation launch");

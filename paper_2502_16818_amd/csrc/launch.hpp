@@ -34,11 +34,13 @@ template <typename S>
 hipError_t launch_step_fused(const void* fin, void* fout, const KParams& K, const KParams* Kd,
                              hipStream_t st);
 
-// Adjoint (kernels_adjoint.hip).
+// Adjoint (kernels_adjoint.hip).  tau_part: one double per block
+// (stage_adjoint_blocks), the block sums of the launch's tau term.
+int stage_adjoint_blocks(const KParams& K);
 template <typename S>
 hipError_t launch_stage_adjoint(const void* f, const void* lam, const void* lam_add, void* out,
-                                double* tau_part, int tau_blocks, double w_in, double w_add,
-                                const KParams& K, hipStream_t st);
+                                double* tau_part, double w_in, double w_add, const KParams& K,
+                                hipStream_t st);
 template <typename S>
 hipError_t launch_init_adjoint(const double* rho, const double* ux, const double* uy,
                                const double* T, const void* lam, double* g_rho, double* g_ux,
@@ -47,6 +49,7 @@ template <typename S>
 hipError_t launch_moments_adjoint(const void* f, const double* g_rho, const double* g_ux,
                                   const double* g_uy, const double* g_T, void* lam,
                                   const KParams& K, hipStream_t st);
+// dst[0] += scale * sum of part[0 .. nblocks), in a fixed order.
 hipError_t launch_accumulate_scalar(const double* part, int nblocks, double scale, double* dst,
                                     hipStream_t st);
 
