@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--no-paper-runs", action="store_true",
+                    help="skip the Sod tube and Taylor-Green runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="grid side of the oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=6)
@@ -164,6 +166,72 @@ def batched_ensemble(steps, warmup):
     return res
 
 
+# Exact solution of the Sod problem of the tube run (gamma = 1.4, left
+# (rho, u, p) = (1, 0, 1), right (0.125, 0, 0.1)): post-shock density and
+# shock speed.
+SOD_RHO_STAR_R = 0.265574
+SOD_SHOCK_SPEED = 1.752156
+
+
+def tube_and_vortex_runs():
+    """The paper-shaped runs beside the headline: the 500 x 1 Sod tube (FP64,
+    5000 steps to t = 0.1) and the 512 x 512 Taylor-Green vortex (10000 steps
+    to t = 1, FP64 and mixed).  Reports time per step, the Sod shock position
+    against the exact one and the vortex's kinetic-energy decay against
+    exp(-4 nu t), nu = T tau."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2502_16818_amd import FP64, MIXED, Solver
+    out = {}
+    run = W.sod_tube()
+    s = Solver.from_run(run, FP64)
+    f = s.init(run.rho, run.ux, run.uy, run.T)
+    g = s.empty_f()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(f, g, nsteps=run.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    rho = s.moments(g)[0][0].cpu().numpy()
+    x = (np.arange(run.nx) + 0.5) * run.dx
+    level = 0.5 * (SOD_RHO_STAR_R + 0.125)
+    j = int(np.nonzero(rho > level)[0].max())          # last cell above the mid level
+    xs = x[j] + (rho[j] - level) / (rho[j] - rho[j + 1]) * run.dx
+    x_exact = 0.5 + SOD_SHOCK_SPEED * run.dt * run.steps
+    out["sod_500"] = {"steps": run.steps, "ms_per_step": el * 1e3 / run.steps,
+                      "shock_position": xs, "exact": x_exact,
+                      "error_cells": (xs - x_exact) / run.dx}
+    s.close()
+
+    tg = {}
+    finals = {}
+    for prec, name in ((FP64, "fp64"), (MIXED, "mixed")):
+        run = W.taylor_green_2pi()
+        s = Solver.from_run(run, prec)
+        f = s.init(run.rho, run.ux, run.uy, run.T)
+        g = s.empty_f()
+        rho0, ux0, uy0, _ = s.moments(f)
+        ke0 = float((rho0 * (ux0 ** 2 + uy0 ** 2)).sum()) / 2
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(f, g, nsteps=run.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rho1, ux1, uy1, _ = s.moments(g)
+        ke1 = float((rho1 * (ux1 ** 2 + uy1 ** 2)).sum()) / 2
+        nu = run.tau * float(np.mean(run.T))
+        tg[name] = {"ms_per_step": el * 1e3 / run.steps, "ke_ratio": ke1 / ke0,
+                    "ke_ratio_viscous": float(np.exp(-4 * nu * run.dt * run.steps))}
+        finals[name] = ux1.clone()
+        s.close()
+    diff = (finals["mixed"] - finals["fp64"]).norm() / finals["fp64"].norm()
+    tg["mixed_vs_fp64_ux_rel_l2"] = float(diff)
+    tg["steps"] = W.taylor_green_2pi().steps
+    out["taylor_green_512"] = tg
+    return out
+
+
 def run_full_seed(run):
     return int(run.name.rsplit("seed", 1)[-1])
 
@@ -245,6 +313,9 @@ def main():
 
     if not args.no_batch:
         out["batched"] = batched_ensemble(args.batch_steps, args.warmup)
+
+    if not args.no_paper_runs:
+        out["paper_runs"] = tube_and_vortex_runs()
 
     if not args.no_adjoint:
         from paper_2502_16818_amd.rollout import adjoint_forward_ratio
