@@ -113,6 +113,33 @@ def lax_tube(nx: int = 1000, dx: float = 2e-3, dt: float = 2e-5, tau: float = 1e
                steps, rho, ux, uy, T)
 
 
+def paper_sod_tube(t_end: float = 0.02) -> Run:
+    """The Sec. 3.1 Sod tube at the paper's shape: 1500 x 1 cells of 1e-4 on
+    [0, 0.15], diaphragm at 0.075, dt = 2e-5, tau = 1e-4, gamma = 2 (I = 0),
+    Sec. 3.1 velocity set, zero-gradient ends.  The end time is not stated;
+    t_end = 0.02 keeps every wave inside the tube."""
+    nx, dx, dt = 1500, 1e-4, 2e-5
+    x = cell_centres(nx, dx)
+    rho, ux, uy, T = _two_state(nx, 1, x, 0.075, (1.0, 0.0, 0.0, 1.0), (0.125, 0.0, 0.0, 0.8))
+    v, eta = VELOCITY_SETS["sod"]
+    return Run("paper_sod", nx, 1, dx, dx, dt, 1e-4, 2.0, v, eta, ZERO_GRADIENT, PERIODIC,
+               int(round(t_end / dt)), rho, ux, uy, T)
+
+
+def paper_shock_tube(t_end: float = 0.04, tau: float = 2e-6) -> Run:
+    """The Sec. 3.3 Ma = 15 shock at the paper's shape: 10000 x 1 cells of
+    2e-4 on [0, 2], post-shock state for x <= 0.02, dt = 2e-6, gamma = 1.4,
+    Sec. 3.3 velocity set, zero-gradient ends.  tau and the end time are not
+    stated; tau = dt and t_end = 0.04 (the shock moves about 0.71)."""
+    nx, dx, dt = 10000, 2e-4, 2e-6
+    x = cell_centres(nx, dx)
+    rho, ux, uy, T = _two_state(nx, 1, x, 0.02, (5.8696, 14.7245, 0.0, 44.6938),
+                                (1.0, 0.0, 0.0, 1.0))
+    v, eta = VELOCITY_SETS["shock"]
+    return Run("paper_shock", nx, 1, dx, dx, dt, tau, 1.4, v, eta, ZERO_GRADIENT, PERIODIC,
+               int(round(t_end / dt)), rho, ux, uy, T)
+
+
 def taylor_green_paper(n: int = 100, t_end: float = 0.1, dt: float = 2e-5) -> Run:
     """The Sec. 3.5 Taylor-Green vortex on [0, 2L]^2 at t = 0 (Eqs. (22)-(24)).
 
