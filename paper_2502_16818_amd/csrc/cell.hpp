@@ -152,15 +152,13 @@ __device__ __forceinline__ void equilibrium(const Macro& m, const KParams& K, do
     }
 }
 
-// z (f - f^eq) for the 16 velocities, formed in the parity basis:
-// with g the parity combinations of f and B m-hat the (row-scaled) block
-// contraction, the scaled parity combinations of f - f^eq are
-// s_r g_r - rho (B m-hat)_r (s_r = 1/2 for axis, 1/4 for diagonal groups),
-// and unpacking them gives f_i - f_i^eq.  `zs2` = z/2 and `zs4` = z/4 fold
-// the relaxation factor into that step.
-__device__ __forceinline__ void relaxation(const Parity& g, const Macro& m, const KParams& K,
-                                           double a, double zs2, double zs4, double out[NV],
-                                           int z = 0) {
+// k (f - f^eq) for the 16 velocities, k = 2 for the axis groups and 4 for
+// the diagonal ones, formed in the parity basis: with g the parity
+// combinations of f and B m-hat the (row-scaled by 1/k) block contraction,
+// the parity combinations of k (f - f^eq) are g_r - k rho (B m-hat)_r, and
+// unpacking them (additions only) gives k (f_i - f_i^eq).
+__device__ __forceinline__ void nonequilibrium(const Parity& g, const Macro& m, const KParams& K,
+                                               double a, double out[NV], int z = 0) {
     const double ux = m.ux, uy = m.uy, T = m.T;
     const double ux2 = ux * ux, uy2 = uy * uy, u2 = ux2 + uy2, uxy = ux * uy;
     const double aT = a * T;
@@ -170,16 +168,16 @@ __device__ __forceinline__ void relaxation(const Parity& g, const Macro& m, cons
     const double moe[4] = {ux, ux * A2, ux * (ux2 + 3.0 * T), ux * (uy2 + T)};
     const double meo[4] = {uy, uy * A2, uy * (ux2 + T), uy * (uy2 + 3.0 * T)};
     const double moo[2] = {uxy, uxy * A4};
-    const double rz = -m.rho * (zs2 + zs2);   // -rho z
-    // scale of each parity component: ee (a, a, b, c, c, d), oe/eo (a, b, c, d), oo (b, d)
+    const double n2 = -2.0 * m.rho, n4 = -4.0 * m.rho;
+    // group of each parity component (k = 2 for a and c, 4 for b and d):
+    // ee (a, a, b, c, c, d), oe/eo (a, b, c, d), oo (b, d)
     double tee[6], toe[4], teo[4], too[2];
 #pragma unroll
     for (int r = 0; r < 6; ++r) {
         double s = K.iee[r][z];
 #pragma unroll
         for (int c = 1; c < 6; ++c) s = fma(K.iee[r][c + z], mee[c], s);
-        const double sc = (r == 2 || r == 5) ? zs4 : zs2;
-        tee[r] = fma(rz, s, sc * g.ee[r]);
+        tee[r] = fma((r == 2 || r == 5) ? n4 : n2, s, g.ee[r]);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -189,13 +187,13 @@ __device__ __forceinline__ void relaxation(const Parity& g, const Macro& m, cons
             so = fma(K.ioe[r][c + z], moe[c], so);
             se = fma(K.ieo[r][c + z], meo[c], se);
         }
-        const double sc = (r & 1) ? zs4 : zs2;
-        toe[r] = fma(rz, so, sc * g.oe[r]);
-        teo[r] = fma(rz, se, sc * g.eo[r]);
+        const double n = (r & 1) ? n4 : n2;
+        toe[r] = fma(n, so, g.oe[r]);
+        teo[r] = fma(n, se, g.eo[r]);
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r)
-        too[r] = fma(rz, fma(K.ioo[r][z], moo[0], K.ioo[r][1 + z] * moo[1]), zs4 * g.oo[r]);
+        too[r] = fma(n4, fma(K.ioo[r][z], moo[0], K.ioo[r][1 + z] * moo[1]), g.oo[r]);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int a0 = 8 * q, d0 = 8 * q + 4;

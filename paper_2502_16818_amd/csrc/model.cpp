@@ -226,6 +226,11 @@ int build_params(const cdbm_params& p, KParams& k, std::string& err) {
     k.a = 2.0 + extra_dof(p.gamma);
     k.inv_a = 1.0 / k.a;
     k.z = p.dt / p.tau;
+    for (int h = 0; h < 2; ++h)
+        for (int grp = 0; grp < 2; ++grp) {
+            k.nzq[h][grp] = -k.z * (h ? 0.5 : 1.0) * (grp ? 0.25 : 0.5);
+            k.nzqf[h][grp] = (float)k.nzq[h][grp];
+        }
     k.dt = p.dt;
     k.tau = p.tau;
     k.nx = p.nx;

@@ -54,6 +54,11 @@ struct KParams {
     double a;                  // D + I
     double inv_a;              // 1 / (D + I)
     double z;                  // dt / tau
+    // -z/2 (axis groups) and -z/4 (diagonal groups) for the first Runge-Kutta
+    // stage, then halved for the second: the factors that turn the output of
+    // nonequilibrium() into -z (f - f^eq).
+    double nzq[2][2];
+    float nzqf[2][2];
     double dt, tau;
     int32_t nx, ny, bcx, bcy;
 };

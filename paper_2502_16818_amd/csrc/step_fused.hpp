@@ -74,6 +74,13 @@ __device__ __forceinline__ S stage_coef_y(const KParams& K, int i, int z) {
     else return HALF ? K.cyh[i + z] : K.cy[i + z];
 }
 
+// -z/2 (axis groups, grp 0) or -z/4 (diagonal groups, grp 1) of a stage.
+template <typename S, bool HALF>
+__device__ __forceinline__ S stage_relax(const KParams& K, int grp, int z) {
+    if constexpr (sizeof(S) == 4) return K.nzqf[HALF][grp + z];
+    else return K.nzq[HALF][grp + z];
+}
+
 // Reads of one ring buffer around one cell.  Offsets are compile-time after
 // unrolling; only one of (ox, oy) is ever nonzero.
 template <typename S, int W>
@@ -105,9 +112,10 @@ __device__ __forceinline__ void stage_cell_k(const Ld& ld, const KParams& K, S o
     Parity g;
     to_parity(fd, g);
     const Macro m = macro_from_parity(g, K, (&K.inv_a)[z], z);
-    const double zr = (&K.z)[z] * (HALF ? 0.5 : 1.0);
-    double coll[NV];
-    relaxation(g, m, K, (&K.a)[z], 0.5 * zr, 0.25 * zr, coll, z);
+    double neq[NV];
+    nonequilibrium(g, m, K, (&K.a)[z], neq, z);
+    // -z / k of the stage, k = 2 (axis groups) or 4 (diagonal groups)
+    const S nza = stage_relax<S, HALF>(K, 0, z), nzd = stage_relax<S, HALF>(K, 1, z);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         S adv = S(0);
@@ -123,7 +131,7 @@ __device__ __forceinline__ void stage_cell_k(const Ld& ld, const KParams& K, S o
         else if (SY[i] < 0)
             adv += stage_coef_y<S, HALF>(K, i, z) *
                    nnd_neg<S>(ld(i, 0, -1), f[i], ld(i, 0, 1), ld(i, 0, 2));
-        const S d = adv - (S)coll[i];
+        const S d = fma((i & 4) ? nzd : nza, (S)neq[i], adv);
         out[i] = HALF ? fma(S(0.5), f[i], d) : f[i] + d;
     }
 }
