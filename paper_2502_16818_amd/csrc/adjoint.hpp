@@ -33,6 +33,40 @@
 
 namespace cdbm {
 
+// Parity form h of f^eq (f^eq = unpacking of h, see equilibrium()).
+__device__ __forceinline__ void equilibrium_parity(const Macro& m, const KParams& K, double a,
+                                                   Parity& h) {
+    const double ux = m.ux, uy = m.uy, T = m.T;
+    const double ux2 = ux * ux, uy2 = uy * uy, u2 = ux2 + uy2, uxy = ux * uy;
+    const double aT = a * T;
+    const double A2 = u2 + aT + 2.0 * T;
+    const double A4 = A2 + 2.0 * T;
+    const double mee[6] = {1.0, u2 + aT, ux2 + T, uy2 + T, ux2 * A4 + T * A2, uy2 * A4 + T * A2};
+    const double moe[4] = {ux, ux * A2, ux * (ux2 + 3.0 * T), ux * (uy2 + T)};
+    const double meo[4] = {uy, uy * A2, uy * (ux2 + T), uy * (uy2 + 3.0 * T)};
+    const double moo[2] = {uxy, uxy * A4};
+#pragma unroll
+    for (int r = 0; r < 6; ++r) {
+        double s = K.iee[r][0];
+#pragma unroll
+        for (int c = 1; c < 6; ++c) s = fma(K.iee[r][c], mee[c], s);
+        h.ee[r] = m.rho * s;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        double so = 0.0, se = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            so = fma(K.ioe[r][c], moe[c], so);
+            se = fma(K.ieo[r][c], meo[c], se);
+        }
+        h.oe[r] = m.rho * so;
+        h.eo[r] = m.rho * se;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) h.oo[r] = m.rho * fma(K.ioo[r][0], moo[0], K.ioo[r][1] * moo[1]);
+}
+
 // Minmod selection of Eq. (16) as (alpha, beta) in {0, 1}.
 template <typename R>
 __device__ __forceinline__ void minmod_select(R X, R Y, double& alpha, double& beta) {
@@ -46,11 +80,10 @@ struct Quad {
     double rho, ux, uy, T;
 };
 
-// (d f^eq / d q)^T a for q = (rho, u_x, u_y, T) at the state m.
-__device__ __forceinline__ Quad equilibrium_vjp_q(const Macro& m, const KParams& K, double a,
-                                                 const double adj[NV]) {
-    Parity hb;
-    to_parity(adj, hb);   // P^T a
+// (d f^eq / d q)^T a for q = (rho, u_x, u_y, T) at the state m, from the
+// parity transform hb = P^T a of a.
+__device__ __forceinline__ Quad equilibrium_vjp_q_parity(const Macro& m, const KParams& K,
+                                                        double a, const Parity& hb) {
     // w = B^T hb per block
     double wee[6], woe[4], weo[4], woo[2];
 #pragma unroll
@@ -123,6 +156,14 @@ __device__ __forceinline__ Quad equilibrium_vjp_q(const Macro& m, const KParams&
     return Quad{gr, m.rho * gx, m.rho * gy, m.rho * gT};
 }
 
+// (d f^eq / d q)^T a for q = (rho, u_x, u_y, T) at the state m.
+__device__ __forceinline__ Quad equilibrium_vjp_q(const Macro& m, const KParams& K, double a,
+                                                 const double adj[NV]) {
+    Parity hb;
+    to_parity(adj, hb);   // P^T a
+    return equilibrium_vjp_q_parity(m, K, a, hb);
+}
+
 // (d q / d f)^T g at the state m, velocity k: q = (rho, u_x, u_y, T).
 __device__ __forceinline__ double moments_vjp_k(const Macro& m, const KParams& K, double a,
                                                 const Quad& g, int k) {
@@ -139,6 +180,10 @@ __device__ __forceinline__ double moments_vjp_k(const Macro& m, const KParams& K
 // the global index of a position only decides which gathers a
 // zero-gradient side skips.
 constexpr int ATX = 64, ATY = 4, AH = 3;
+// Velocity groups of a stage-adjoint block: each group of ATX x ATY threads
+// takes every AG-th velocity, so a block keeps AG waves per 64 cells busy.
+constexpr int AG = 2;
+static_assert(NV % AG == 0, "every group must run the same number of velocity steps");
 constexpr int ATW = ATX + 2 * AH, ATH = ATY + 2 * AH;
 
 template <typename S>

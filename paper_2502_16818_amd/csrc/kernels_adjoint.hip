@@ -12,27 +12,34 @@ namespace {
 // out = w_add * add + w_in * E'(g)^T a, and the per-block partial sums of
 // w_in * sum_i a_i dE_i/dtau = w_in * sum_i a_i dt (g_i - g_i^eq) / tau^2.
 // The state g is in the storage precision S; adjoint vectors are double.
-// A block handles ATX x ATY cells.  The pointwise part (equilibrium and
-// moment transposes) reads the cell's 16 values directly; the NND transposes
-// run one velocity at a time on a tile of g_i and a_i with a 3-cell halo
-// staged in LDS, so that every value a gather needs is loaded from HBM once
-// per block instead of once per use.
+// A block handles ATX x ATY cells with AG groups of ATX x ATY threads.  The
+// pointwise part (macroscopic state, equilibrium transpose, tau term) runs
+// one thread per cell, split over two groups, and is shared through LDS.
+// The NND transposes then run one velocity per group at a time (group k
+// takes velocities k, k + AG, ...) on a tile of g_i and a_i with a 3-cell
+// halo staged in LDS, so that every value a gather needs is loaded from HBM
+// once per block instead of once per use, and the groups keep AG times as
+// many waves busy as cells alone would.
 template <typename S>
-__global__ void __launch_bounds__(ATX * ATY) k_stage_adjoint(const S* __restrict__ g,
-                                                             const double* __restrict__ a,
-                                                             const double* __restrict__ add,
-                                                             double* __restrict__ out, double w_in,
-                                                             double w_add, KParams K,
-                                                             double* __restrict__ tau_part) {
-    constexpr int NT = ATX * ATY;
+__global__ void __launch_bounds__(ATX * ATY * AG) k_stage_adjoint(const S* __restrict__ g,
+                                                                  const double* __restrict__ a,
+                                                                  const double* __restrict__ add,
+                                                                  double* __restrict__ out,
+                                                                  double w_in, double w_add,
+                                                                  KParams K,
+                                                                  double* __restrict__ tau_part) {
+    constexpr int NC = ATX * ATY;               // cells per block
     constexpr int TILE = ATW * ATH;
-    constexpr int PER = (TILE + NT - 1) / NT;   // tile elements per thread
-    __shared__ S Ft[TILE];
-    __shared__ double At[TILE];
-    __shared__ unsigned char Sx[TILE], Sy[TILE];   // face selections along x and y
-    __shared__ double red[NT];
+    constexpr int PER = (TILE + NC - 1) / NC;   // tile elements per thread of a group
+    __shared__ S Ft[AG][TILE];
+    __shared__ double At[AG][TILE];
+    __shared__ unsigned char Sx[AG][TILE], Sy[AG][TILE];   // face selections along x and y
+    __shared__ double Mq[8][NC];                            // rho, u_x, u_y, T, then q
+    __shared__ double red[NC];
     const int tid = threadIdx.x;
-    const int lx = tid % ATX, ly = tid / ATX;
+    const int grp = __builtin_amdgcn_readfirstlane(tid / NC);   // uniform per wave
+    const int cid = tid % NC;
+    const int lx = cid % ATX, ly = cid / ATX;
     const int x0 = blockIdx.x * ATX, y0 = blockIdx.y * ATY;
     const int x = x0 + lx, y = y0 + ly;
     const int nx = K.nx, ny = K.ny;
@@ -40,89 +47,132 @@ __global__ void __launch_bounds__(ATX * ATY) k_stage_adjoint(const S* __restrict
     const bool inside = x < nx && y < ny;
 
     // the tile elements this thread stages: source offset within a plane, or
-    // -1 for a zero-gradient ghost (adjoint 0 there)
+    // a zero-gradient ghost (adjoint 0 there)
     int64_t src[PER];
     bool ghost[PER];
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-        const int idx = tid + e * NT;
+        const int idx = cid + e * NC;
         const int tx = idx % ATW, ty = idx / ATW;
         const int gx = x0 - AH + tx, gy = y0 - AH + ty;
         src[e] = (int64_t)wrap_or_clamp(gy, ny, K.bcy) * nx + wrap_or_clamp(gx, nx, K.bcx);
         ghost[e] = (K.bcx != CDBM_PERIODIC && (gx < 0 || gx >= nx)) ||
                    (K.bcy != CDBM_PERIODIC && (gy < 0 || gy >= ny));
     }
-
-    // pointwise part: macroscopic state, equilibrium transpose and the tau term
-    Macro m{};
-    Quad q{};
-    double tpart = 0.0;
-    const int64_t c = (int64_t)y * nx + x;
-    if (inside) {
-        double gd[NV], ad[NV], feq[NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            gd[i] = (double)g[i * cells + c];
-            ad[i] = a[i * cells + c];
-        }
-        Parity pg;
-        to_parity(gd, pg);
-        m = macro_from_parity(pg, K, K.inv_a);
-        equilibrium(m, K, K.a, feq);
-        q = equilibrium_vjp_q(m, K, K.a, ad);
-        const double tau2 = K.dt / (K.tau * K.tau);
-#pragma unroll
-        for (int i = 0; i < NV; ++i) tpart = fma(ad[i], tau2 * (gd[i] - feq[i]), tpart);
-    }
-    const SelLine Srow{Sx + (ly + AH) * ATW, 1}, Scol{Sy + lx + AH, ATW};
-    const TileLine<double> Arow{At + (ly + AH) * ATW, 1}, Acol{At + lx + AH, ATW};
-    // tile values of the next velocity, loaded while the current one is used
+    // tile values of the group's next velocity, loaded while the current one is used
     S fnext[PER];
     double anext[PER];
     auto fetch = [&](int i) {
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            if (tid + e * NT < TILE) {
+            if (cid + e * NC < TILE) {
                 fnext[e] = g[i * cells + src[e]];
                 anext[e] = ghost[e] ? 0.0 : a[i * cells + src[e]];
             }
         }
     };
-    fetch(0);
-    for (int i = 0; i < NV; ++i) {
+    // pointwise part: group 0 the state and the tau term, group 1 the
+    // equilibrium transpose, both from the parity transforms pg = P g and
+    // pa = P a (P P^T = k I per group, k = 2 axis, 4 diagonal).  With h the
+    // parity form of f^eq (f^eq = P^T h), a . (g - f^eq) = pa . (pg / k - h).
+    const int64_t c = (int64_t)y * nx + x;
+    double tpart = 0.0;
+    if (grp < 2 && inside) {
+        Parity pg, pa;
+        {
+            double v[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v[i] = (double)g[i * cells + c];
+            to_parity(v, pg);
+        }
+        {
+            double v[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v[i] = a[i * cells + c];
+            to_parity(v, pa);
+        }
+        const Macro m = macro_from_parity(pg, K, K.inv_a);
+        if (grp == 0) {
+            Parity h;
+            equilibrium_parity(m, K, K.a, h);
+            double d = 0.0;
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+                d = fma(pa.ee[r], fma((r == 2 || r == 5) ? 0.25 : 0.5, pg.ee[r], -h.ee[r]), d);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const double k = (r & 1) ? 0.25 : 0.5;
+                d = fma(pa.oe[r], fma(k, pg.oe[r], -h.oe[r]), d);
+                d = fma(pa.eo[r], fma(k, pg.eo[r], -h.eo[r]), d);
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) d = fma(pa.oo[r], fma(0.25, pg.oo[r], -h.oo[r]), d);
+            tpart = (K.dt / (K.tau * K.tau)) * d;
+            Mq[0][cid] = m.rho;
+            Mq[1][cid] = m.ux;
+            Mq[2][cid] = m.uy;
+            Mq[3][cid] = m.T;
+        } else {
+            const Quad q = equilibrium_vjp_q_parity(m, K, K.a, pa);
+            Mq[4][cid] = q.rho;
+            Mq[5][cid] = q.ux;
+            Mq[6][cid] = q.uy;
+            Mq[7][cid] = q.T;
+        }
+    }
+    fetch(grp);
+    __syncthreads();
+    Macro m{};
+    Quad q{};
+    if (inside) {
+        m = Macro{Mq[0][cid], Mq[1][cid], Mq[2][cid], Mq[3][cid]};
+        q = Quad{Mq[4][cid], Mq[5][cid], Mq[6][cid], Mq[7][cid]};
+    }
+    S* const F = Ft[grp];
+    double* const Ag = At[grp];
+    unsigned char* const Sxg = Sx[grp];
+    unsigned char* const Syg = Sy[grp];
+    const SelLine Srow{Sxg + (ly + AH) * ATW, 1}, Scol{Syg + lx + AH, ATW};
+    const TileLine<double> Arow{Ag + (ly + AH) * ATW, 1}, Acol{Ag + lx + AH, ATW};
+    // every group runs NV / AG iterations, so all threads meet every barrier
+#pragma unroll 1
+    for (int i = grp; i < NV; i += AG) {
         __syncthreads();   // the previous velocity's tiles are no longer read
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            const int idx = tid + e * NT;
+            const int idx = cid + e * NC;
             if (idx < TILE) {
-                Ft[idx] = fnext[e];
-                At[idx] = anext[e];
+                F[idx] = fnext[e];
+                Ag[idx] = anext[e];
             }
         }
-        if (i + 1 < NV) fetch(i + 1);
+        if (i + AG < NV) fetch(i + AG);
         __syncthreads();
+        const int sx = SX[i & (NV - 1)], sy = SY[i & (NV - 1)];
         // selection of every tile position with both line neighbours in the tile
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
-            const int idx = tid + e * NT;
+            const int idx = cid + e * NC;
             if (idx < TILE) {
                 const int tx = idx % ATW, ty = idx / ATW;
-                if (SX[i] != 0 && tx > 0 && tx < ATW - 1)
-                    Sx[idx] = face_code<S>(Ft[idx - 1], Ft[idx], Ft[idx + 1]);
-                if (SY[i] != 0 && ty > 0 && ty < ATH - 1)
-                    Sy[idx] = face_code<S>(Ft[idx - ATW], Ft[idx], Ft[idx + ATW]);
+                if (sx != 0 && tx > 0 && tx < ATW - 1)
+                    Sxg[idx] = face_code<S>(F[idx - 1], F[idx], F[idx + 1]);
+                if (sy != 0 && ty > 0 && ty < ATH - 1)
+                    Syg[idx] = face_code<S>(F[idx - ATW], F[idx], F[idx + ATW]);
             }
         }
         __syncthreads();
         if (inside) {
             const double ceq = moments_vjp_k(m, K, K.a, q, i);
             double adv = 0.0;
-            if (SX[i] != 0)
-                adv += K.cx[i] * (SX[i] > 0 ? nnd_transpose<true>(Srow, Arow, lx + AH, x, nx, K.bcx)
-                                            : nnd_transpose<false>(Srow, Arow, lx + AH, x, nx, K.bcx));
-            if (SY[i] != 0)
-                adv += K.cy[i] * (SY[i] > 0 ? nnd_transpose<true>(Scol, Acol, ly + AH, y, ny, K.bcy)
-                                            : nnd_transpose<false>(Scol, Acol, ly + AH, y, ny, K.bcy));
+            if (sx > 0)
+                adv += K.cx[i] * nnd_transpose<true>(Srow, Arow, lx + AH, x, nx, K.bcx);
+            else if (sx < 0)
+                adv += K.cx[i] * nnd_transpose<false>(Srow, Arow, lx + AH, x, nx, K.bcx);
+            if (sy > 0)
+                adv += K.cy[i] * nnd_transpose<true>(Scol, Acol, ly + AH, y, ny, K.bcy);
+            else if (sy < 0)
+                adv += K.cy[i] * nnd_transpose<false>(Scol, Acol, ly + AH, y, ny, K.bcy);
             const double ai = Arow.at(lx + AH);   // a_i at the cell
             double v = ai + adv - K.z * (ai - ceq);
             v *= w_in;
@@ -130,10 +180,9 @@ __global__ void __launch_bounds__(ATX * ATY) k_stage_adjoint(const S* __restrict
             out[i * cells + c] = v;
         }
     }
-    tpart *= w_in;
-    red[tid] = tpart;
+    if (grp == 0) red[cid] = tpart * w_in;
     __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
+    for (int s = NC / 2; s > 0; s >>= 1) {
         if (tid < s) red[tid] += red[tid + s];
         __syncthreads();
     }
@@ -215,7 +264,7 @@ hipError_t launch_stage_adjoint(const void* g, const void* a, const void* add, v
                                 double* tau_part, double w_in, double w_add, const KParams& K,
                                 hipStream_t st) {
     const dim3 grid(blocks_for(K.nx, ATX), blocks_for(K.ny, ATY));
-    hipLaunchKernelGGL(k_stage_adjoint<S>, grid, dim3(ATX * ATY), 0, st, (const S*)g, (const double*)a,
+    hipLaunchKernelGGL(k_stage_adjoint<S>, grid, dim3(ATX * ATY * AG), 0, st, (const S*)g, (const double*)a,
                        (const double*)add, (double*)out, w_in, w_add, K, tau_part);
     return hipGetLastError();
 }
