@@ -3,8 +3,13 @@
 // Same pipeline as fused_strip (step_fused.hpp), with a strip of TX = 120
 // output columns handled by two waves per row (64 columns each) and R = 6
 // rows per iteration, so that a block still has 12 waves:
-//   F0: f^n rows, TX + 8 = 128 columns;  F1: f^(1) rows, TX + 4 = 124 columns;
-//   ring depth R + 4 = 10 rows each (158 KB of LDS).
+//   F0: f^n rows, TX + 8 = 128 columns;  F1: f^(1) rows, TX + 4 = 124 columns
+//   stored at a stride of 128;  ring depth R + 4 = 10 rows each (160 KB of
+//   LDS, all of it).  With both strides at 512 bytes the rows of successive
+//   velocities are two 256-byte steps apart, so every LDS read of a cell's
+//   16 velocities (and every store of its f^(1)) uses one base address and
+//   paired reads with immediate offsets; the 124-float stride needed an
+//   address computation every other velocity.
 // A row of f^n is fetched from HBM as 16 contiguous 512-byte segments (one
 // per velocity), twice the length of the 60-column strip's segments, and
 // stage 1 is recomputed on the same 4 halo columns for twice the outputs.
@@ -24,7 +29,7 @@ struct WideGeom {
     static constexpr int WPR = 2;            // waves per row
     static constexpr int R = 6;              // rows per iteration
     static constexpr int W0 = TX + 8;        // F0 row width
-    static constexpr int W1 = TX + 4;        // F1 row width
+    static constexpr int W1 = TX + 8;        // F1 row stride (TX + 4 columns used)
     static constexpr int SLOTS = R + 4;
     static constexpr int NT = R * WPR * 64;
     static constexpr int F0_ELEMS = SLOTS * NV * W0;
