@@ -143,6 +143,25 @@ def cpu_baseline(run_full, side, steps):
                       f"{el:.1f} s"}
 
 
+def copy_bandwidth(torch, nbytes=COPY_BYTES, reps=20):
+    """Read + write GB/s of a plain 1 GiB device-to-device tensor copy."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del a, c
+    return 2 * nbytes / t / 1e9
+
+
 def batched_ensemble(steps, warmup):
     """The 96-grid ensemble (sizes 128..1024, own gamma and tau per grid) in
     the mixed form, one persistent launch per step."""
@@ -297,6 +316,10 @@ def main():
     })
     del fa, fb
     s.close()
+    # the same bytes against a plain device copy on this GPU (read + write)
+    copy_gbs = copy_bandwidth(torch)
+    out["roofline"]["copy_GBs"] = copy_gbs
+    out["roofline"]["frac_of_copy"] = achieved / copy_gbs
 
     if not args.no_fp64:
         s = Solver.from_run(run, FP64)

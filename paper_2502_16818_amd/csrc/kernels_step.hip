@@ -11,9 +11,12 @@ namespace cdbm {
 
 namespace {
 
-// pieces > 0: block b takes strip b % nstrips and the (b / nstrips)-th of
-// `pieces` equal row ranges, so that blocks on neighbouring strips stream the
-// same rows at the same time (their row segments share DRAM pages).
+// pieces > 0: block number L takes strip L % nstrips and the (L / nstrips)-th
+// of `pieces` equal row ranges, so that blocks on neighbouring strips stream
+// the same rows at the same time (their row segments share DRAM pages).
+// Blocks are numbered XCD by XCD (the hardware deals them out to the 8 XCDs
+// in turn), so the blocks of one XCD hold consecutive strips and read the
+// halo columns they share through that XCD's L2 once.
 // pieces == 0: block b takes the b-th of gridDim.x equal, contiguous pieces of
 // the strip-major sequence of (strip, row) pairs.
 template <typename S, bool VEC>
@@ -29,7 +32,13 @@ __global__ void __launch_bounds__(StripKernel<S>::NT) k_step_fused(const S* __re
     // this block's range [u, u1) of the strip-major sequence of (strip, row)
     int64_t u, u1;
     if (pieces > 0) {
-        const int s = blockIdx.x % nstrips, p = blockIdx.x / nstrips;
+        // blocks go to the 8 XCDs round-robin; number them XCD by XCD so that
+        // the blocks of one XCD take consecutive strips of the same rows and
+        // share the halo columns in that XCD's L2
+        const int G = gridDim.x, b = blockIdx.x;
+        const int xq = G / 8, xr = G % 8, xcd = b % 8;
+        const int L = xcd * xq + min(xcd, xr) + b / 8;
+        const int s = L % nstrips, p = L / nstrips;
         const int len = (K.ny + pieces - 1) / pieces;
         u = (int64_t)s * K.ny + min(K.ny, p * len);
         u1 = (int64_t)s * K.ny + min(K.ny, (p + 1) * len);
