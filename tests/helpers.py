@@ -46,3 +46,54 @@ def to_np(t):
     if isinstance(t, torch.Tensor):
         return t.detach().cpu().double().numpy()
     return np.asarray(t)
+
+
+# Oracle steps on patches (the full-size parity tests).  f^{n+1} at a cell
+# depends on f^n only within 4 cells along x or along y (two Runge-Kutta
+# stages of the 2-cell NND stencil), so the oracle's step on the 9 x 9 patch
+# around the cell, cut from the GPU's own f^n, gives the cell's exact f^{n+1}
+# whatever boundary the patch itself gets.  At a zero-gradient x side the
+# patch is clipped to the domain and gets that boundary.
+PATCH_HALO = 4
+# max |difference| / max |f| of the patch, by precision form (0 FP64, 1 mixed).
+# Mixed: f^{n+1} and f^(1) are rounded to FP32 (half an ulp each, 6e-8 of
+# |f|) and the advection runs in FP32 on increments much smaller than f.
+FP64_MIXED_PATCH_TOL = {0: 1e-12, 1: 3e-7}
+
+
+def patch_indices(run, x, y):
+    """Columns and rows of the 9 x 9 patch around (x, y), the centre's
+    position in it and the patch's x boundary (y must be periodic)."""
+    nx, ny = run.nx, run.ny
+    h = PATCH_HALO
+    w = 2 * h + 1
+    if run.bc_x == C.ZERO_GRADIENT and x < h:
+        cols, cx, bcx = np.arange(0, w), x, C.ZERO_GRADIENT
+    elif run.bc_x == C.ZERO_GRADIENT and x >= nx - h:
+        cols, cx, bcx = np.arange(nx - w, nx), x - (nx - w), C.ZERO_GRADIENT
+    else:
+        cols, cx, bcx = np.arange(x - h, x + h + 1) % nx, h, C.PERIODIC
+    assert run.bc_y == C.PERIODIC
+    rows = np.arange(y - h, y + h + 1) % ny
+    return cols, rows, cx, h, bcx
+
+
+def check_patch_step(run, f_prev, f_next, cells, precision, tol=None):
+    """Compare f_next at each (x, y) of `cells` with the oracle's step of the
+    patch of f_prev around it; returns the worst relative error."""
+    tol = FP64_MIXED_PATCH_TOL[precision] if tol is None else tol
+    p0 = C.Params.from_run(run)
+    worst = 0.0
+    for x, y in cells:
+        cols, rows, cx, cy, bcx = patch_indices(run, x, y)
+        ci = torch.as_tensor(cols, device=f_prev.device)
+        ri = torch.as_tensor(rows, device=f_prev.device)
+        fp = f_prev.index_select(1, ri).index_select(2, ci).double().cpu()
+        p = C.Params(len(cols), len(rows), p0.dx, p0.dy, p0.dt, p0.tau, p0.I, p0.v, p0.eta,
+                     bcx, C.PERIODIC)
+        want = C.step(fp, p)[:, cy, cx]
+        got = f_next[:, y, x].double().cpu()
+        err = float((got - want).abs().max() / fp.abs().max())
+        worst = max(worst, err)
+        assert err <= tol, (x, y, err)
+    return worst

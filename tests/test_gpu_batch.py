@@ -5,7 +5,7 @@ import torch
 
 from oracle import cdbm as C
 import workloads as W
-from helpers import oracle_after, rel_max, to_np
+from helpers import check_patch_step, oracle_after, rel_max, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -83,13 +83,24 @@ def test_batch_rejects_inconsistent_velocity_sets():
 
 
 def test_batched_ensemble_workload_runs_and_conserves_mass():
-    """The 96-grid ensemble (sizes 128..1024) in the mixed form: 20 steps,
-    finite, and total mass of each periodic grid conserved to FP32 rounding."""
+    """The 96-grid ensemble (sizes 128..1024) in the mixed form: one step
+    against the oracle on sampled cells (see check_patch_step), then 20
+    steps, finite, and total mass of each periodic grid conserved to FP32
+    rounding."""
     from paper_2502_16818_amd import Batch, Solver
     runs = W.batched_ensemble()
     b = Batch(_params(runs, MIXED))
     f = b.init([(r.rho, r.ux, r.uy, r.T) for r in runs])
     m0 = [b.view(f, k).double().sum().item() for k in range(len(runs))]
+    # one step of the whole ensemble, in the launch the benchmark times,
+    # against oracle patch steps on sampled cells of every eighth grid
+    f1 = b.step(f)
+    rng = np.random.default_rng(96)
+    for k in range(0, len(runs), 8):
+        r = runs[k]
+        cells = [(0, 0), (r.nx - 1, r.ny - 1), (119, int(rng.integers(0, r.ny))),
+                 (int(rng.integers(0, r.nx)), int(rng.integers(0, r.ny)))]
+        check_patch_step(r, b.view(f, k), b.view(f1, k), cells, MIXED)
     out = b.step(f, nsteps=20)
     assert torch.isfinite(out).all()
     for k in range(len(runs)):

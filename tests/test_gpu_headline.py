@@ -18,13 +18,9 @@ import torch
 
 import workloads as W
 from oracle import cdbm as C
+from helpers import check_patch_step as _check_step
 
 FP64, MIXED = 0, 1
-HALO = 4
-# max |difference| / max |f| of the patch.  Mixed form: f^{n+1} and f^(1) are
-# rounded to FP32 (half an ulp each, 6e-8 of |f|) and the advection runs in
-# FP32 on increments much smaller than f: a few ulp at most.
-TOL = {FP64: 1e-12, MIXED: 3e-7}
 
 
 def _sample_cells(nx, ny, rng):
@@ -43,41 +39,6 @@ def _sample_cells(nx, ny, rng):
     cells += [(int(rng.integers(0, nx)), int(rng.integers(0, ny))) for _ in range(24)]
     cells += [(0, 0), (nx - 1, ny - 1), (0, ny - 1), (nx - 1, 0)]
     return cells
-
-
-def _patch(run, x, y):
-    """Column and row indices of the 9 x 9 patch, the centre's position in it
-    and the patch's x boundary."""
-    nx, ny = run.nx, run.ny
-    w = 2 * HALO + 1
-    if run.bc_x == W.ZERO_GRADIENT and x < HALO:
-        cols, cx, bcx = np.arange(0, w), x, C.ZERO_GRADIENT
-    elif run.bc_x == W.ZERO_GRADIENT and x >= nx - HALO:
-        cols, cx, bcx = np.arange(nx - w, nx), x - (nx - w), C.ZERO_GRADIENT
-    else:
-        cols, cx, bcx = np.arange(x - HALO, x + HALO + 1) % nx, HALO, C.PERIODIC
-    assert run.bc_y == W.PERIODIC
-    rows = np.arange(y - HALO, y + HALO + 1) % ny
-    return cols, rows, cx, HALO, bcx
-
-
-def _check_step(run, f_prev, f_next, cells, precision, tol=None):
-    tol = TOL[precision] if tol is None else tol
-    p0 = C.Params.from_run(run)
-    worst = 0.0
-    for x, y in cells:
-        cols, rows, cx, cy, bcx = _patch(run, x, y)
-        ci = torch.as_tensor(cols, device=f_prev.device)
-        ri = torch.as_tensor(rows, device=f_prev.device)
-        fp = f_prev.index_select(1, ri).index_select(2, ci).double().cpu()
-        p = C.Params(len(cols), len(rows), p0.dx, p0.dy, p0.dt, p0.tau, p0.I, p0.v, p0.eta,
-                     bcx, C.PERIODIC)
-        want = C.step(fp, p)[:, cy, cx]
-        got = f_next[:, y, x].double().cpu()
-        err = float((got - want).abs().max() / fp.abs().max())
-        worst = max(worst, err)
-        assert err <= tol, (x, y, err)
-    return worst
 
 
 def test_patch_step_equals_full_grid_step():
