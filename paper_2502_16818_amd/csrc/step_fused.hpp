@@ -1,19 +1,22 @@
 // Fused two-stage Runge-Kutta step of the CDBM (both stages in one pass
 // over HBM).
 //
-// A block owns a strip of TX = 60 output columns and streams down the grid
-// in y, R rows per iteration (one wave per row), keeping two ring buffers of
-// R + 4 rows in LDS:
-//   F0: f^n rows, TX + 8 columns (x halo of 4 each side);
-//   F1: f^(1) = f^n + dt L(f^n) rows, TX + 4 columns.
+// A block owns a strip of TX = 56 output columns and streams down the grid
+// in y, R = 6 rows per iteration (one wave per row), keeping two ring
+// buffers of R + 4 rows in LDS:
+//   F0: f^n rows, TX + 8 = 64 columns (x halo of 4 each side);
+//   F1: f^(1) = f^n + dt L(f^n) rows, TX + 4 = 60 columns at a stride of 64.
+// In FP64 both rows are 512 bytes, so one base address and immediate
+// offsets serve the LDS accesses of all 16 velocities of a cell, and the two
+// rings fill the 160 KB of LDS.
 // Iteration t (rows relative to the segment start):
 //   load  f^n    rows [4 + (t-2)R, 4 + (t-1)R)   (global -> registers -> F0)
 //   stage 1      rows [2 + (t-2)R, 2 + (t-1)R)   (F0 -> F1; one cell per thread)
 //   stage 2      rows [(t-2)R, (t-1)R)           (F1, F0 -> f^{n+1} in HBM)
 // Each stage runs just two rows behind what it needs, so R + 4 rows of each
 // ring are live at once; each f value crosses HBM once in and once out per
-// step, and stage 1 is recomputed only on the 2-column x halo (64 columns
-// for 60 outputs).  The global loads of iteration t+1 are issued during
+// step, and stage 1 is recomputed only on the 2-column x halo (60 columns
+// for 56 outputs).  The global loads of iteration t+1 are issued during
 // iteration t, in two halves: before stage 1 and before stage 2.  This strip
 // serves FP64 storage; FP32 storage uses the wider strip of step_wide.hpp.
 //
@@ -32,33 +35,26 @@
 
 namespace cdbm {
 
-constexpr int FUSED_TX = 60;               // output columns per strip
-constexpr int FUSED_W0 = FUSED_TX + 8;     // F0 row width
-constexpr int FUSED_W1 = FUSED_TX + 4;     // F1 row width (= 64 = one wave)
-
-// Rows per iteration: one wave per row.  The ring depth R + 4 must be a
-// power of two.  With FP64 storage, 4 rows (256 threads, 132 KB of LDS, one
-// block per compute unit); 12 rows would fit FP32 storage (132 KB, three
-// waves per SIMD), which the wide strip of step_wide.hpp serves instead.
+// Geometry of the strip: TX output columns; F0 rows hold TX + 8 columns of
+// f^n (4 halo columns each side), F1 rows the TX + 4 columns of f^(1) that
+// stage 2 reads; both rows are 64 elements (512 bytes in FP64), one column
+// per lane.  R rows per iteration, one wave per row; ring depth R + 4.
+// FP64: 56 outputs, 6 rows (384 threads, all 160 KB of LDS).  The wider
+// 60-column strip with 4 rows (one wave per SIMD) left every LDS and barrier
+// latency exposed and was 6 % slower.
 template <typename S>
-struct FusedRows;
+struct FusedGeom;
 template <>
-struct FusedRows<float> {
-    static constexpr int R = 12;
-};
-template <>
-struct FusedRows<double> {
-    static constexpr int R = 4;
-};
-
-template <typename S>
-struct FusedGeom {
-    static constexpr int R = FusedRows<S>::R;
+struct FusedGeom<double> {
+    static constexpr int TX = 56;
+    static constexpr int W0 = 64;
+    static constexpr int W1 = 64;
+    static constexpr int R = 6;
     static constexpr int SLOTS = R + 4;
     static constexpr int NT = R * 64;
-    static constexpr int F0_ELEMS = SLOTS * NV * FUSED_W0;
-    static constexpr int F1_ELEMS = SLOTS * NV * FUSED_W1;
-    static_assert((SLOTS & (SLOTS - 1)) == 0, "ring depth must be a power of two");
+    static constexpr int F0_ELEMS = SLOTS * NV * W0;
+    static constexpr int F1_ELEMS = SLOTS * NV * W1;
+    static_assert(W0 == TX + 8 && W1 >= TX + 4 && W1 <= 64, "one column per lane");
 };
 
 // NND coefficients -dt v_ir / dr of a stage: HALF selects the halved ones of
@@ -209,10 +205,11 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
     using V = typename Chunk<S>::type;
     constexpr int R = G::R;
     constexpr int SLOTS = G::SLOTS;
+    constexpr int TX = G::TX, W0 = G::W0, W1 = G::W1;
     constexpr int CW = 16 / (int)sizeof(S);        // elements per chunk
-    constexpr int LCH = FUSED_W0 / CW;             // chunks per loaded velocity row
+    constexpr int LCH = W0 / CW;                   // chunks per loaded velocity row
     constexpr int NLD = (NV * LCH + 63) / 64;      // chunk loads per lane and row
-    static_assert(FUSED_W0 % CW == 0 && FUSED_TX % CW == 0 && 4 % CW == 0, "chunk geometry");
+    static_assert(W0 % CW == 0 && TX % CW == 0 && 4 % CW == 0, "chunk geometry");
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // 0..R-1, uniform
@@ -221,7 +218,7 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
     const int nrows = yb - ya;
 
     // ring slot of a row given relative to ya (rows >= -4 - R are ever used)
-    auto slot = [&](int q) { return (q + 4 * SLOTS) & (SLOTS - 1); };
+    auto slot = [&](int q) { return (q + 4 * SLOTS) % SLOTS; };
 
     // Chunk c = k * 64 + lane of a row: velocity c / per_row, chunk c % per_row.
     // Lanes past the last chunk repeat it (the same value to the same place).
@@ -245,13 +242,11 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
 
     // wave w loads row 4 + (t-2)R + w (all 16 velocities) at iteration t;
     // only rows -4 .. nrows+3 are needed
-    constexpr int NPRE = VEC ? NLD : 2 * NV;
+    constexpr int NPRE = VEC ? NLD : NV;
     using P = typename std::conditional<VEC, V, S>::type;
     P pre[NPRE];
-    // per-column form: global columns this lane loads into F0 (lanes 0..63,
-    // plus 64..67 on lanes 0..3)
+    // per-column form: the global column this lane loads into F0
     const int gc_a = VEC ? 0 : map_index(x0 - 4 + lane, nx, bcx);
-    const int gc_b = VEC ? 0 : map_index(x0 - 4 + 64 + (lane & 3), nx, bcx);
     auto load_row = [&](int t) { return 4 + (t - 2) * R + wave; };
     auto wanted = [&](int q) { return q >= -4 && q < nrows + 4; };
     // loads of part `half` (0 or 1) of the row of iteration t
@@ -269,25 +264,21 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
             for (int i = 0; i < NV; ++i) {
                 if ((i < NV / 2 ? 0 : 1) != half) continue;
                 pre[i] = src[(int64_t)i * cells + gc_a];
-                pre[NV + i] = (lane < 4) ? src[(int64_t)i * cells + gc_b] : S(0);
             }
         }
     };
     auto store_loads = [&](int t) {
         const int q = load_row(t);
         if (!wanted(q)) return;
-        S* dst = F0 + slot(q) * NV * FUSED_W0;
+        S* dst = F0 + slot(q) * NV * W0;
         if constexpr (VEC) {
-            // chunk c sits at element c * CW of the slot (FUSED_W0 = LCH * CW)
+            // chunk c sits at element c * CW of the slot (W0 = LCH * CW)
 #pragma unroll
             for (int k = 0; k < NLD; ++k)
                 *(V*)(dst + min(k * 64 + lane, NV * LCH - 1) * CW) = pre[k];
         } else {
 #pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                dst[i * FUSED_W0 + lane] = pre[i];
-                if (lane < 4) dst[i * FUSED_W0 + 64 + lane] = pre[NV + i];
-            }
+            for (int i = 0; i < NV; ++i) dst[i * W0 + lane] = pre[i];
         }
     };
 
@@ -305,20 +296,21 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
         // stage 1: f^(1) at row q1, column x0 - 2 + lane
         const int q1 = 2 + (t - 2) * R + wave;
         if (q1 >= -2 && q1 < nrows + 2) {
-            RingLd<S, FUSED_W0> ld;
+            RingLd<S, W0> ld;
             ld.ring = F0;
             const int x1 = x0 - 2 + lane;
 #pragma unroll
             for (int o = -2; o <= 2; ++o) {
                 ld.slot[o + 2] = slot(q1 + o);
-                ld.col[o + 2] = (bcx == CDBM_ZERO_GRADIENT) ? min(max(x1 + o, 0), nx - 1) - (x0 - 4)
-                                                            : lane + 2 + o;
+                const int c = (bcx == CDBM_ZERO_GRADIENT) ? min(max(x1 + o, 0), nx - 1) - (x0 - 4)
+                                                          : lane + 2 + o;
+                ld.col[o + 2] = min(c, W0 - 1);   // lanes past the window read in bounds
             }
             S out[NV];
             stage_cell_k<S, false>(ld, K, out);
-            S* dst = F1 + slot(q1) * NV * FUSED_W1 + lane;
+            S* dst = F1 + slot(q1) * NV * W1 + lane;
 #pragma unroll
-            for (int i = 0; i < NV; ++i) dst[i * FUSED_W1] = out[i];
+            for (int i = 0; i < NV; ++i) dst[i * W1] = out[i];
         }
         lds_barrier();
 
@@ -328,22 +320,22 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
         if (q2 >= 0 && q2 < nrows) {
             const int r2 = ya + q2;
             const int x = x0 + lane;
-            RingLd<S, FUSED_W1> ld;
+            RingLd<S, W1> ld;
             ld.ring = F1;
 #pragma unroll
             for (int o = -2; o <= 2; ++o) {
                 const int rr = (bcy == CDBM_ZERO_GRADIENT) ? min(max(r2 + o, 0), ny - 1) : r2 + o;
                 const int cc = (bcx == CDBM_ZERO_GRADIENT) ? min(max(x + o, 0), nx - 1) : x + o;
                 ld.slot[o + 2] = slot(rr - ya);
-                ld.col[o + 2] = min(max(cc - (x0 - 2), 0), FUSED_W1 - 1);
+                ld.col[o + 2] = min(max(cc - (x0 - 2), 0), W1 - 1);
             }
             S out[NV];
             stage_cell_k<S, true>(ld, K, out);
-            if (lane < FUSED_TX && x < nx) {
-                const S* fn = F0 + slot(q2) * NV * FUSED_W0 + 4 + lane;   // f^n of the cell
+            if (lane < TX && x < nx) {
+                const S* fn = F0 + slot(q2) * NV * W0 + 4 + lane;   // f^n of the cell
                 S* dst = fout + (int64_t)r2 * nx + x;
 #pragma unroll
-                for (int i = 0; i < NV; ++i) dst[(int64_t)i * cells] = fma(S(0.5), fn[i * FUSED_W0], out[i]);
+                for (int i = 0; i < NV; ++i) dst[(int64_t)i * cells] = fma(S(0.5), fn[i * W0], out[i]);
             }
         }
     }

@@ -11,8 +11,7 @@
 //   paired reads with immediate offsets; the 124-float stride needed an
 //   address computation every other velocity.
 // A row of f^n is fetched from HBM as 16 contiguous 512-byte segments (one
-// per velocity), twice the length of the 60-column strip's segments, and
-// stage 1 is recomputed on the same 4 halo columns for twice the outputs.
+// per velocity), and stage 1 is recomputed on 4 halo columns for 120 outputs.
 // Wave (r, h) of a row r handles columns [64h, 64h + 64) of the strip's
 // stage-1 and stage-2 windows.  The global loads of the next rows are issued
 // in two halves, before stage 1 and before stage 2, and each lane stores its
@@ -184,7 +183,7 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
 namespace cdbm {
 
 // The strip kernel of each storage type: FP32 uses the wide strip, FP64
-// (twice the LDS per row) the 60-column strip of fused_strip.
+// (twice the LDS per row) the 56-column strip of fused_strip.
 template <typename S>
 struct StripKernel;
 template <>
@@ -200,7 +199,7 @@ struct StripKernel<float> {
 template <>
 struct StripKernel<double> {
     using G = FusedGeom<double>;
-    static constexpr int TX = FUSED_TX, NT = G::NT;
+    static constexpr int TX = G::TX, NT = G::NT;
     static constexpr int F0_ELEMS = G::F0_ELEMS, F1_ELEMS = G::F1_ELEMS;
     template <bool VEC>
     static __device__ __forceinline__ void run(const double* fin, double* fout, const KParams& K,
