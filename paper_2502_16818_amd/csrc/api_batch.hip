@@ -121,10 +121,12 @@ int cdbm_batch_create(const cdbm_params* per_grid, int32_t ngrids, const int64_t
     b->elem = b->precision == CDBM_MIXED ? sizeof(float) : sizeof(double);
 
     std::vector<int64_t> work(ngrids + 1, 0);
+    int64_t strip_rows = 0;
     for (int g = 0; g < ngrids; ++g) {
         const int tx = strip_width(b->precision);
         const int64_t strips = (per_grid[g].nx + tx - 1) / tx;
-        work[g + 1] = work[g] + strips * per_grid[g].ny;
+        strip_rows += strips * per_grid[g].ny;
+        work[g + 1] = work[g] + strips * (per_grid[g].ny + BATCH_FILL);
     }
     hipError_t e = hipGetDevice(&b->device);
     if (e != hipSuccess) {
@@ -148,7 +150,7 @@ int cdbm_batch_create(const cdbm_params* per_grid, int32_t ngrids, const int64_t
         release(b);
         return hip_fail(e, "hipMemcpy of the batch tables");
     }
-    const int64_t cap = (work[ngrids] + 31) / 32;
+    const int64_t cap = (strip_rows + 31) / 32;
     int64_t nb = b->precision == CDBM_MIXED ? batch_blocks<float>() : batch_blocks<double>();
     b->nblocks = (int)std::max<int64_t>(1, std::min(nb, cap));
     // the chunked form of the step (16-byte chunks, 32-bit offsets within a grid)

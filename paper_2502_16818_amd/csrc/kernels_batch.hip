@@ -1,8 +1,11 @@
 // Batched ensemble step: one persistent launch advances every grid of the
 // batch by one time step.  The work of all grids is laid out as one sequence
-// of (grid, strip, row) triples (grid-major); block b takes the b-th of
-// gridDim.x equal contiguous pieces, so the load is balanced in strip-rows
-// however uneven the grids are.  Each grid has its own constants (sizes,
+// of (grid, strip, row) triples (grid-major), each strip weighted by its rows
+// plus BATCH_FILL for the pipeline fill of a segment; block number L takes
+// the L-th of gridDim.x equal contiguous pieces, so the load is balanced
+// however uneven the grids are.  Blocks are numbered XCD by XCD (the
+// hardware deals them out to the 8 XCDs in turn), so neighbouring pieces,
+// which hold neighbouring strips, share an L2.  Each grid has its own constants (sizes,
 // dt/tau, D + I, dx, dy, boundary conditions) in a device table; the
 // velocity set, and so the inverse moment matrix, is shared.
 #include <hip/hip_runtime.h>
@@ -25,18 +28,27 @@ __global__ void __launch_bounds__(StripKernel<S>::NT) k_batch_step(const S* __re
     __shared__ __attribute__((aligned(16))) S F0[SK::F0_ELEMS];
     __shared__ __attribute__((aligned(16))) S F1[SK::F1_ELEMS];
     const int64_t total = work_start[ngrids];
-    const int64_t u1 = total * (blockIdx.x + 1) / gridDim.x;
-    int64_t u = total * blockIdx.x / gridDim.x;
+    const int G = gridDim.x, b = blockIdx.x;   // block number L, XCD by XCD
+    const int xq = G / 8, xr = G % 8, xcd = b % 8;
+    const int L = xcd * xq + min(xcd, xr) + b / 8;
+    const int64_t u1 = total * (L + 1) / G;
+    int64_t u = total * L / G;
     int g = 0;
     while (u < u1) {
         while (work_start[g + 1] <= u) ++g;   // grids are visited in order
         const KParams& K = Ks[g];
+        // strip s of grid g spans BATCH_FILL + ny positions: the pipeline fill
+        // of a segment, then one position per row
+        const int64_t len = (int64_t)K.ny + BATCH_FILL;
         const int64_t v = u - work_start[g];
-        const int s = (int)(v / K.ny);
-        const int ya = (int)(v - (int64_t)s * K.ny);
-        const int yb = (int)min((int64_t)K.ny, (int64_t)ya + (u1 - u));
-        SK::template run<VEC>(fin + f_off[g], fout + f_off[g], K, s * SK::TX, ya, yb, F0, F1);
-        u += yb - ya;
+        const int s = (int)(v / len);
+        const int64_t p0 = (int64_t)s * len;
+        const int64_t e = min(p0 + len, min(u1, work_start[g + 1]) - work_start[g]);
+        const int ya = (int)max((int64_t)0, v - p0 - BATCH_FILL);
+        const int yb = (int)max((int64_t)0, e - p0 - BATCH_FILL);
+        if (ya < yb)
+            SK::template run<VEC>(fin + f_off[g], fout + f_off[g], K, s * SK::TX, ya, yb, F0, F1);
+        u = work_start[g] + e;
     }
 }
 

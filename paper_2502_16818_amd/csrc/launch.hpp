@@ -55,9 +55,13 @@ hipError_t launch_accumulate_scalar(const double* part, int nblocks, double scal
 
 // Batched ensemble (kernels_batch.hip).  Ks: per-grid constants (device);
 // f_off: element offset of each grid's f block (device); work_start: prefix
-// sums of the grids' strip-row counts, ngrids + 1 entries (device).
+// sums of the grids' weighted strip counts, strips * (ny + BATCH_FILL),
+// ngrids + 1 entries (device).
 template <typename S>
 int batch_blocks();
+// Positions a strip of the batch split weighs beyond its rows: the pipeline
+// fill of a segment, in rows.
+constexpr int BATCH_FILL = 14;
 // Output columns per strip of the fused step for a precision form.
 int strip_width(int precision);
 // chunked: every grid's width and element offset is a multiple of the
