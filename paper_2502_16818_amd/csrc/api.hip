@@ -188,7 +188,8 @@ int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
     h->cells = (int64_t)p->nx * p->ny;
     h->elem = mixed(h) ? sizeof(float) : sizeof(double);
     h->fbytes = (size_t)cdbm::NV * (size_t)h->cells * h->elem;
-    const int tau_blocks = ((p->nx + 63) / 64) * ((p->ny + 3) / 4);
+    // tau partials of the two stage adjoints of a step, side by side
+    const int tau_blocks = 2 * stage_adjoint_blocks(h->k);
     h->split = p->step_form == CDBM_STEP_SPLIT ||
                (p->step_form == CDBM_STEP_AUTO && h->cells <= SPLIT_STEP_CELLS);
     if (ensure_buffer(h, &h->scratch) != CDBM_OK ||

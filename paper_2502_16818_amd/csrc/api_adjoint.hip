@@ -6,7 +6,8 @@
 //   lam^n = lam' / 2 + E'(f)^T mu
 //   dL/dtau += lam' . dE/dtau(f1) / 2 + mu . dE/dtau(f)
 // f1 is recomputed from f (the unfused stage kernel) into the handle's stage
-// buffer; mu lives in a second handle-owned buffer.  Adjoint vectors are
+// buffer; mu lives in a second handle-owned buffer.  The two stage adjoints
+// leave their per-block tau partials side by side, summed by one launch.  Adjoint vectors are
 // double in both precision forms: for a loss of the density alone lam_i is
 // close to one value for all i, and the gradient with respect to u and T is
 // carried by its small deviations, which FP32 storage would round away.
@@ -29,11 +30,10 @@ int step_adjoint_impl(cdbm_handle* h, const void* f_n, const void* lam_np1, void
     if (e != hipSuccess) return hip_fail(e, "stage recompute launch");
     e = launch_stage_adjoint<S>(h->stage, lam_np1, nullptr, h->lam_mid, h->tau_part, 0.5, 0.0, K, st);
     if (e != hipSuccess) return hip_fail(e, "stage adjoint launch");
-    e = launch_accumulate_scalar(h->tau_part, nb, 1.0, dtau, st);
-    if (e != hipSuccess) return hip_fail(e, "tau accumulation launch");
-    e = launch_stage_adjoint<S>(f_n, h->lam_mid, lam_np1, lam_n, h->tau_part, 1.0, 0.5, K, st);
+    e = launch_stage_adjoint<S>(f_n, h->lam_mid, lam_np1, lam_n, h->tau_part + nb, 1.0, 0.5, K, st);
     if (e != hipSuccess) return hip_fail(e, "stage adjoint launch");
-    e = launch_accumulate_scalar(h->tau_part, nb, 1.0, dtau, st);
+    // both stages' tau partials in one fixed-order sum
+    e = launch_accumulate_scalar(h->tau_part, 2 * nb, 1.0, dtau, st);
     if (e != hipSuccess) return hip_fail(e, "tau accumulation launch");
     return CDBM_OK;
 }

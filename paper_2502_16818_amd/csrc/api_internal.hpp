@@ -42,7 +42,7 @@ struct cdbm_handle {
     bool split = false;         // step as two single-stage launches (small grids)
     void* lam_mid = nullptr;    // f-sized buffer for the adjoint's intermediate product
     double* partials = nullptr; // reduction partials
-    double* tau_part = nullptr; // per-block partial sums of the adjoint's tau term
+    double* tau_part = nullptr; // per-block partial sums of the adjoint's tau term (two stages)
     cdbm::KParams* kdev = nullptr;   // device copy of k
     int* flag = nullptr;        // device flag of the field check
     cdbm::StepGraph graph;
