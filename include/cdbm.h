@@ -79,7 +79,8 @@ enum { CDBM_STEP_AUTO = 0, CDBM_STEP_FUSED = 1, CDBM_STEP_SPLIT = 2 };
  *               CDBM_STEP_SPLIT: two single-stage launches, one cell per
  *               thread, f^(1) through a handle-owned buffer (faster on small
  *               grids, where the fused launch has too few strips to fill the
- *               chip).  CDBM_STEP_AUTO: split up to 512 x 512 cells, fused
+ *               chip).  CDBM_STEP_AUTO: split up to 2^19 cells (724 x 724)
+ *               in the mixed form and 2^18 (512 x 512) in FP64, fused
  *               above.  Ignored by the batched form (always fused). */
 typedef struct cdbm_params {
     int32_t nx, ny;

@@ -134,9 +134,11 @@ namespace {
 
 // With CDBM_STEP_AUTO, grids of up to this many cells take the step as two
 // single-stage launches (f^(1) through the handle's stage buffer): one cell
-// per thread fills the chip, where the fused step has too few strip pieces
-// to hide its latency.
-constexpr int64_t SPLIT_STEP_CELLS = int64_t(1) << 18;   // 512 x 512
+// per thread fills the chip, where the fused step has too few rows per block
+// to hide its per-iteration latency (measured crossovers: about 700 x 700
+// cells in the mixed form, about 560 x 560 in FP64).
+constexpr int64_t SPLIT_STEP_CELLS_MIXED = int64_t(1) << 19;   // 724 x 724
+constexpr int64_t SPLIT_STEP_CELLS_FP64 = int64_t(1) << 18;    // 512 x 512
 
 hipError_t step_once(const cdbm_handle* h, const void* fin, void* fout, hipStream_t st) {
     if (h->split) {
@@ -191,7 +193,8 @@ int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
     // tau partials of the two stage adjoints of a step, side by side
     const int tau_blocks = 2 * stage_adjoint_blocks(h->k);
     h->split = p->step_form == CDBM_STEP_SPLIT ||
-               (p->step_form == CDBM_STEP_AUTO && h->cells <= SPLIT_STEP_CELLS);
+               (p->step_form == CDBM_STEP_AUTO &&
+                h->cells <= (mixed(h) ? SPLIT_STEP_CELLS_MIXED : SPLIT_STEP_CELLS_FP64));
     if (ensure_buffer(h, &h->scratch) != CDBM_OK ||
         (h->split && ensure_buffer(h, &h->stage) != CDBM_OK) ||
         hipMalloc(&h->partials, sizeof(double) * 4 * REDUCE_BLOCKS) != hipSuccess ||
