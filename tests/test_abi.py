@@ -95,3 +95,24 @@ def test_null_arguments_are_rejected(lib):
     assert lib.cdbm_create(None, ctypes.byref(h)) == -1
     assert lib.cdbm_step(None, None, None, 1, None) == -1
     assert lib.cdbm_destroy(None) == 0
+
+
+def test_batch_create_rejects_bad_tables(lib):
+    """Checked before any device allocation: no grids, a negative offset,
+    overlapping f blocks, grids with different velocity sets."""
+    P = type(_params())
+    b = ctypes.c_void_p()
+    two = (P * 2)(_params(), _params())
+    off_ok = (ctypes.c_int64 * 2)(0, 16 * 16 * 8)
+    assert lib.cdbm_batch_create(two, 0, off_ok, ctypes.byref(b)) == -1
+    assert not b.value
+    neg = (ctypes.c_int64 * 2)(0, -8)
+    assert lib.cdbm_batch_create(two, 2, neg, ctypes.byref(b)) == -1
+    assert b"negative" in lib.cdbm_last_error()
+    overlap = (ctypes.c_int64 * 2)(0, 16 * 16 * 8 - 1)
+    assert lib.cdbm_batch_create(two, 2, overlap, ctypes.byref(b)) == -1
+    assert b"overlap" in lib.cdbm_last_error()
+    mixed_sets = (P * 2)(_params(), _params(v=(1.5, 1.1, 1.1, 1.0)))
+    assert lib.cdbm_batch_create(mixed_sets, 2, off_ok, ctypes.byref(b)) == -1
+    assert b"same for every grid" in lib.cdbm_last_error()
+    assert not b.value
