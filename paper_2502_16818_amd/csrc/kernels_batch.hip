@@ -10,6 +10,8 @@
 // velocity set, and so the inverse moment matrix, is shared.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "launch.hpp"
 #include "step_wide.hpp"
 
@@ -56,20 +58,17 @@ __global__ void __launch_bounds__(StripKernel<S>::NT) k_batch_step(const S* __re
 
 template <typename S>
 int batch_blocks() {
-    static int g = -1;
-    if (g < 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-            return 256;
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<S, true>, StripKernel<S>::NT, 0) !=
-                hipSuccess ||
+    // resident blocks per compute unit (the same on every gfx950 device)
+    static std::atomic<int> per_cu{0};
+    int nb = per_cu.load(std::memory_order_relaxed);
+    if (nb < 1) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<S, true>,
+                                                         StripKernel<S>::NT, 0) != hipSuccess ||
             nb < 1)
             nb = 1;
-        g = nb * prop.multiProcessorCount;
+        per_cu.store(nb, std::memory_order_relaxed);
     }
-    return g;
+    return nb * device_cus();
 }
 
 template <typename S>

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "launch.hpp"
 #include "step_wide.hpp"
@@ -65,14 +66,7 @@ struct Launch {
 // with one block per compute unit takes contiguous pieces of the work.
 template <typename S>
 Launch fused_launch(const KParams& K) {
-    static int cus = -1;
-    if (cus < 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-            return Launch{256, 0};
-        cus = prop.multiProcessorCount;   // one block per compute unit (LDS-bound)
-    }
+    const int cus = device_cus();   // one block per compute unit (LDS-bound)
     constexpr int TX = StripKernel<S>::TX;
     const int nstrips = (K.nx + TX - 1) / TX;
     if (sizeof(S) == 4) {
@@ -89,6 +83,21 @@ Launch fused_launch(const KParams& K) {
 }
 
 }  // namespace
+
+int device_cus() {
+    constexpr int MAX_DEVICES = 64;
+    static std::atomic<int> cache[MAX_DEVICES] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return 256;
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess || prop.multiProcessorCount < 1)
+        return 256;
+    n = prop.multiProcessorCount;
+    cache[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
 
 template <typename S>
 hipError_t launch_step_fused(const void* fin, void* fout, const KParams& K, const KParams* Kd,

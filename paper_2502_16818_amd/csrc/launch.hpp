@@ -28,6 +28,10 @@ template <typename S>
 hipError_t launch_stage(const void* fin, const void* base, void* fout, bool stage2,
                         const KParams& K, const KParams* Kd, hipStream_t st);
 
+// Compute units of the current device (cached per device; 256 if the query
+// fails).
+int device_cus();
+
 // Fused two-stage step (kernels_step.hip).  K: host copy (launch geometry);
 // Kd: the same constants in device memory (read by the kernel).
 template <typename S>
