@@ -75,6 +75,12 @@ void StepGraph::drop() {
     out = nullptr;
 }
 
+void StepGraph::release() {
+    drop();
+    if (cap) (void)hipStreamDestroy(cap);
+    cap = nullptr;
+}
+
 int run_steps(StepFn fn, const void* ctx, const void* fin, void* fout, void* scratch, int nsteps,
               hipStream_t st, StepGraph& graph) {
     int remaining = nsteps;
@@ -91,18 +97,25 @@ int run_steps(StepFn fn, const void* ctx, const void* fin, void* fout, void* scr
     }
     // remaining is even and the state is in fout
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    const bool can_graph = st != nullptr && hipStreamIsCapturing(st, &cs) == hipSuccess &&
-                           cs == hipStreamCaptureStatusNone;
+    const bool can_graph =
+        st == nullptr || (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone);
     if (can_graph && remaining >= GRAPH_STEPS) {
         if (!graph.exec || graph.out != fout) {
             graph.drop();
+            if (!graph.cap) {
+                e = hipStreamCreateWithFlags(&graph.cap, hipStreamNonBlocking);
+                if (e != hipSuccess) {
+                    graph.cap = nullptr;
+                    return hip_fail(e, "hipStreamCreateWithFlags");
+                }
+            }
             hipGraph_t g = nullptr;
-            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            e = hipStreamBeginCapture(graph.cap, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
             hipError_t le = hipSuccess;
             for (int s = 0; s < GRAPH_STEPS && le == hipSuccess; ++s)
-                le = (s % 2 == 0) ? fn(ctx, fout, scratch, st) : fn(ctx, scratch, fout, st);
-            e = hipStreamEndCapture(st, &g);
+                le = (s % 2 == 0) ? fn(ctx, fout, scratch, graph.cap) : fn(ctx, scratch, fout, graph.cap);
+            e = hipStreamEndCapture(graph.cap, &g);
             if (le != hipSuccess || e != hipSuccess) {
                 if (g) (void)hipGraphDestroy(g);
                 return hip_fail(le != hipSuccess ? le : e, "step graph capture");
@@ -216,7 +229,7 @@ int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
 int cdbm_destroy(cdbm_handle* h) {
     if (!h) return CDBM_OK;
     (void)hipDeviceSynchronize();
-    h->graph.drop();
+    h->graph.release();
     if (h->scratch) (void)hipFree(h->scratch);
     if (h->stage) (void)hipFree(h->stage);
     if (h->lam_mid) (void)hipFree(h->lam_mid);

@@ -38,7 +38,7 @@ struct cdbm_batch {
 namespace {
 
 void release(cdbm_batch* b) {
-    b->graph.drop();
+    b->graph.release();
     if (b->d_k) (void)hipFree(b->d_k);
     if (b->d_off) (void)hipFree(b->d_off);
     if (b->d_work) (void)hipFree(b->d_work);

@@ -21,10 +21,15 @@ constexpr int REDUCE_BLOCKS = 1024;
 using StepFn = hipError_t (*)(const void* ctx, const void* fin, void* fout, hipStream_t st);
 
 // Captured graph of an even number of steps ping-ponging out -> scratch -> out.
+// The steps are captured on a stream of the handle's own (`cap`, created on
+// first use), so that the graph also serves callers on the null stream; the
+// graph is then launched on the caller's stream.
 struct StepGraph {
     hipGraphExec_t exec = nullptr;
     void* out = nullptr;
-    void drop();
+    hipStream_t cap = nullptr;
+    void drop();      // the instantiated graph
+    void release();   // the graph and the capture stream
 };
 
 
@@ -57,8 +62,8 @@ int check_fields_range(int* flag, const double* rho, const double* ux, const dou
 
 // Advance nsteps >= 1 from fin to fout (destinations alternate between fout
 // and scratch and end on fout; fin is never written).  Long runs replay a
-// captured graph when the stream is a non-null stream that is not itself
-// being captured.
+// captured graph on `st`, unless `st` is itself being captured (then every
+// step is launched directly into the caller's capture).
 int run_steps(StepFn fn, const void* ctx, const void* fin, void* fout, void* scratch,
               int nsteps, hipStream_t st, StepGraph& graph);
 }  // namespace cdbm

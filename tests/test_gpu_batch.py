@@ -72,6 +72,28 @@ def test_batch_is_bitwise_equal_to_single_grid_runs(precision, sizes):
         s.close()
 
 
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_batch_graph_replays_match_eager_steps(precision):
+    """cdbm_batch_step replays a captured graph of 32 steps on long runs;
+    every replay must equal the same steps launched one call at a time, also
+    after other work on the batch in between."""
+    from paper_2502_16818_amd import Batch
+    runs = [W.random_periodic(nx, ny, seed=nx) for nx, ny in ((136, 23), (64, 40), (248, 9))]
+    b = Batch(_params(runs, precision))
+    f0 = b.init([(r.rho, r.ux, r.uy, r.T) for r in runs])
+    f = f0.clone()
+    for _ in range(64):
+        f = b.step(f)
+    out = b.empty_f()
+    for rep in range(3):
+        b.step(f0, out, nsteps=64)
+        torch.cuda.synchronize()
+        assert torch.equal(out, f), rep
+        _ = b.step(f0, nsteps=5)
+        torch.cuda.synchronize()
+    b.close()
+
+
 def test_batch_rejects_inconsistent_velocity_sets():
     from paper_2502_16818_amd import Batch, CdbmError
     runs = _mixed_set()[:2]

@@ -147,6 +147,35 @@ def test_fused_and_split_steps_are_bitwise_equal(precision):
         assert torch.equal(outs[0], outs[1]), run.name
 
 
+@pytest.mark.parametrize("form", sorted(FORMS))
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_graph_replays_match_eager_steps(precision, form):
+    """Long cdbm_step calls replay a captured graph of 32 steps (on torch's
+    null stream as well); every replay must equal the same steps launched one
+    call at a time.  The graph is replayed again after other work on the
+    handle and with a longer run (two replays per call)."""
+    run = _chunked_cases()[0]
+    s = _solver(run, precision, FORMS[form])
+    f0 = s.init(run.rho, run.ux, run.uy, run.T)
+    eager = {}
+    f = f0.clone()
+    for k in range(1, 97):
+        f = s.step(f)            # one step per call: no graph
+        if k in (64, 96):
+            eager[k] = f.clone()
+    out = s.empty_f()
+    for rep in range(3):
+        s.step(f0, out, nsteps=64)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager[64]), rep
+        _ = s.moments(s.step(f0, nsteps=3))   # other work on the handle in between
+        torch.cuda.synchronize()
+    s.step(f0, out, nsteps=96)
+    torch.cuda.synchronize()
+    assert torch.equal(out, eager[96])
+    s.close()
+
+
 def test_conserved_totals_periodic_fp64():
     run = W.random_periodic(64, 40, seed=9, dt=1e-4, tau=1e-4)
     s = _solver(run, FP64)
