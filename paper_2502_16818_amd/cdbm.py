@@ -97,13 +97,23 @@ def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
 
-def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+def _ptr(t: Optional[torch.Tensor], dtype: Optional[torch.dtype] = None,
+         numel: Optional[int] = None) -> Optional[int]:
+    """Device address of t after checking what the C ABI cannot: a contiguous
+    tensor on the current GPU, of the element type and (at least) the number
+    of elements the call reads or writes."""
     if t is None:
         return None
     if not t.is_cuda:
         raise ValueError("CDBM buffers must be device tensors")
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError("CDBM buffers must be on the current GPU")
     if not t.is_contiguous():
         raise ValueError("CDBM buffers must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"CDBM buffer has dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"CDBM buffer has {t.numel()} elements, the call needs {numel}")
     return t.data_ptr()
 
 
@@ -161,6 +171,12 @@ class Solver:
     def empty_field(self, *lead) -> torch.Tensor:
         return torch.empty(tuple(lead) + (self.ny, self.nx), dtype=torch.float64, device="cuda")
 
+    def _f(self, t: torch.Tensor) -> int:
+        return _ptr(t, self.dtype, 16 * self.nx * self.ny)
+
+    def _lam(self, t: torch.Tensor) -> int:
+        return _ptr(t, torch.float64, 16 * self.nx * self.ny)
+
     def _field(self, a) -> torch.Tensor:
         t = torch.as_tensor(a, dtype=torch.float64)
         return t.to("cuda").contiguous().reshape(self.ny, self.nx)
@@ -169,29 +185,31 @@ class Solver:
     def init(self, rho, ux, uy, T, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         fs = [self._field(a) for a in (rho, ux, uy, T)]
         out = self.empty_f() if out is None else out
-        _check(load().cdbm_init(self._h, *[_ptr(a) for a in fs], _ptr(out), _stream()), "cdbm_init")
+        _check(load().cdbm_init(self._h, *[_ptr(a) for a in fs], self._f(out), _stream()),
+               "cdbm_init")
         return out
 
     def step(self, f_in: torch.Tensor, f_out: Optional[torch.Tensor] = None,
              nsteps: int = 1) -> torch.Tensor:
         f_out = self.empty_f() if f_out is None else f_out
-        _check(load().cdbm_step(self._h, _ptr(f_in), _ptr(f_out), int(nsteps), _stream()), "cdbm_step")
+        _check(load().cdbm_step(self._h, self._f(f_in), self._f(f_out), int(nsteps), _stream()),
+               "cdbm_step")
         return f_out
 
     def moments(self, f: torch.Tensor) -> Tuple[torch.Tensor, ...]:
         outs = [self.empty_field() for _ in range(4)]
-        _check(load().cdbm_moments(self._h, _ptr(f), *[_ptr(o) for o in outs], _stream()),
+        _check(load().cdbm_moments(self._h, self._f(f), *[_ptr(o) for o in outs], _stream()),
                "cdbm_moments")
         return tuple(outs)
 
     def tne(self, f: torch.Tensor) -> torch.Tensor:
         out = self.empty_field(12)
-        _check(load().cdbm_tne(self._h, _ptr(f), _ptr(out), _stream()), "cdbm_tne")
+        _check(load().cdbm_tne(self._h, self._f(f), _ptr(out), _stream()), "cdbm_tne")
         return out
 
     def totals(self, f: torch.Tensor) -> torch.Tensor:
         out = torch.empty(4, dtype=torch.float64, device="cuda")
-        _check(load().cdbm_conserved_totals(self._h, _ptr(f), _ptr(out), _stream()),
+        _check(load().cdbm_conserved_totals(self._h, self._f(f), _ptr(out), _stream()),
                "cdbm_conserved_totals")
         return out
 
@@ -202,20 +220,17 @@ class Solver:
     def step_adjoint(self, f_n: torch.Tensor, lam_np1: torch.Tensor,
                      lam_n: Optional[torch.Tensor] = None,
                      dtau: Optional[torch.Tensor] = None):
-        if lam_np1.dtype != torch.float64:
-            raise ValueError("adjoint vectors are float64")
         lam_n = self.empty_lam() if lam_n is None else lam_n
         dtau = torch.zeros(1, dtype=torch.float64, device="cuda") if dtau is None else dtau
-        _check(load().cdbm_step_adjoint(self._h, _ptr(f_n), _ptr(lam_np1), _ptr(lam_n), _ptr(dtau),
-                                        _stream()), "cdbm_step_adjoint")
+        _check(load().cdbm_step_adjoint(self._h, self._f(f_n), self._lam(lam_np1), self._lam(lam_n),
+                                        _ptr(dtau, torch.float64, 1), _stream()),
+               "cdbm_step_adjoint")
         return lam_n, dtau
 
     def init_adjoint(self, rho, ux, uy, T, lam_f0: torch.Tensor):
-        if lam_f0.dtype != torch.float64:
-            raise ValueError("adjoint vectors are float64")
         fs = [self._field(a) for a in (rho, ux, uy, T)]
         outs = [self.empty_field() for _ in range(4)]
-        _check(load().cdbm_init_adjoint(self._h, *[_ptr(a) for a in fs], _ptr(lam_f0),
+        _check(load().cdbm_init_adjoint(self._h, *[_ptr(a) for a in fs], self._lam(lam_f0),
                                         *[_ptr(o) for o in outs], _stream()), "cdbm_init_adjoint")
         return tuple(outs)
 
@@ -223,8 +238,8 @@ class Solver:
                         out: Optional[torch.Tensor] = None) -> torch.Tensor:
         gs = [self._field(g) for g in (g_rho, g_ux, g_uy, g_T)]
         out = self.empty_lam() if out is None else out
-        _check(load().cdbm_moments_adjoint(self._h, _ptr(f), *[_ptr(g) for g in gs], _ptr(out),
-                                           _stream()), "cdbm_moments_adjoint")
+        _check(load().cdbm_moments_adjoint(self._h, self._f(f), *[_ptr(g) for g in gs],
+                                           self._lam(out), _stream()), "cdbm_moments_adjoint")
         return out
 
 
@@ -270,16 +285,24 @@ class Batch:
         return f[self.offsets[k]:self.offsets[k] + self.sizes[k]].view(16, p.ny, p.nx)
 
     def init(self, fields: Sequence[Tuple], out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if len(fields) != len(self.params):
+            raise ValueError(f"{len(fields)} field sets for {len(self.params)} grids")
+        for fl, p in zip(fields, self.params):
+            for a in fl:
+                if torch.as_tensor(a).numel() != p.nx * p.ny:
+                    raise ValueError(f"a field of a {p.nx} x {p.ny} grid has {torch.as_tensor(a).numel()} values")
         cat = [torch.cat([torch.as_tensor(fl[q], dtype=torch.float64).reshape(-1) for fl in fields])
-               .to("cuda") for q in range(4)]
+               .to("cuda").contiguous() for q in range(4)]
         out = self.empty_f() if out is None else out
-        _check(load().cdbm_batch_init(self._b, *[_ptr(c) for c in cat], _ptr(out), _stream()),
+        _check(load().cdbm_batch_init(self._b, *[_ptr(c) for c in cat],
+                                      _ptr(out, self.dtype, self.total), _stream()),
                "cdbm_batch_init")
         return out
 
     def step(self, f_in: torch.Tensor, f_out: Optional[torch.Tensor] = None,
              nsteps: int = 1) -> torch.Tensor:
         f_out = self.empty_f() if f_out is None else f_out
-        _check(load().cdbm_batch_step(self._b, _ptr(f_in), _ptr(f_out), int(nsteps), _stream()),
+        _check(load().cdbm_batch_step(self._b, _ptr(f_in, self.dtype, self.total),
+                                      _ptr(f_out, self.dtype, self.total), int(nsteps), _stream()),
                "cdbm_batch_step")
         return f_out

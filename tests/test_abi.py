@@ -116,3 +116,14 @@ def test_batch_create_rejects_bad_tables(lib):
     assert lib.cdbm_batch_create(mixed_sets, 2, off_ok, ctypes.byref(b)) == -1
     assert b"same for every grid" in lib.cdbm_last_error()
     assert not b.value
+
+
+def test_binding_checks_buffers_before_the_call():
+    """The C ABI takes bare pointers; the Python binding checks element type,
+    size, device and layout first (CPU: no handle is needed to reach them)."""
+    import torch
+    from paper_2502_16818_amd import cdbm as B
+    t = torch.zeros(8)
+    with pytest.raises(ValueError, match="device tensors"):
+        B._ptr(t)
+    assert B._ptr(None) is None

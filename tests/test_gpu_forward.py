@@ -176,6 +176,23 @@ def test_graph_replays_match_eager_steps(precision, form):
     s.close()
 
 
+def test_binding_rejects_wrong_buffers():
+    """Wrong element type, too few elements or a strided view never reach the
+    kernels: the binding raises before the call."""
+    run = W.random_periodic(64, 8, seed=3, dt=1e-4, tau=1e-4)
+    s = _solver(run, MIXED)
+    f = s.init(run.rho, run.ux, run.uy, run.T)
+    with pytest.raises(ValueError, match="dtype"):
+        s.step(f.double())
+    with pytest.raises(ValueError, match="elements"):
+        s.step(f[:, :4].contiguous())
+    with pytest.raises(ValueError, match="contiguous"):
+        s.step(f, s.empty_f().transpose(1, 2))
+    with pytest.raises(ValueError, match="float64"):
+        s.step_adjoint(f, torch.zeros_like(f))
+    s.close()
+
+
 def test_conserved_totals_periodic_fp64():
     run = W.random_periodic(64, 40, seed=9, dt=1e-4, tau=1e-4)
     s = _solver(run, FP64)
