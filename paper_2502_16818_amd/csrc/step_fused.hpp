@@ -90,13 +90,39 @@ struct RingLd {
     }
 };
 
+// Makes v available at this point of the program.  Stores that only some
+// lanes perform sit in a branch, and the compiler would otherwise move the
+// arithmetic feeding them into that branch, apart from the lane shifts
+// below, which must run in every lane.
+__device__ __forceinline__ void materialize(float& v) { asm volatile("" : "+v"(v)); }
+
+// Value of a 32-bit register in lane - 1 (from_left) or lane + 1
+// (from_right) of the wave: DPP whole-wave shifts, which the compiler folds
+// into the instruction that uses the value.  Lane 0 (from_left) and lane 63
+// (from_right) receive 0.
+__device__ __forceinline__ float from_left(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_right(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
 // One stage at one cell with every run constant read from K at an opaque
 // zero offset (see opaque_zero).  First stage (HALF = false): returns
 // f + dt L(f).  Second stage (HALF = true): returns (f + dt L(f)) / 2, with
 // the 1/2 folded into the coefficients, so that the Heun combination is
 // f^n / 2 plus the result.
-template <typename S, bool HALF, class Ld>
+//
+// XLANE (FP32 only): the lanes of the wave hold consecutive cells of a row,
+// and the x-direction NND takes the minmod of the neighbouring cell from the
+// neighbouring lane.  Each lane forms M = minmod(f_{j+1} - f_j, f_j - f_{j-1});
+// the positive-velocity difference needs M of lane j - 1 and the negative one
+// M of lane j + 1, so lanes 0 and 63 return garbage and the caller discards
+// them.  The arithmetic is the same as nnd_pos / nnd_neg term by term, so the
+// results are bitwise those of the per-lane form.  All 64 lanes must run it.
+template <typename S, bool HALF, class Ld, bool XLANE = false>
 __device__ __forceinline__ void stage_cell_k(const Ld& ld, const KParams& K, S out[NV]) {
+    static_assert(!XLANE || sizeof(S) == 4, "lane shifts move 32-bit values");
     const int z = opaque_zero();
     S f[NV];
     double fd[NV];
@@ -115,7 +141,15 @@ __device__ __forceinline__ void stage_cell_k(const Ld& ld, const KParams& K, S o
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         S adv = S(0);
-        if (SX[i] > 0)
+        if constexpr (XLANE) {
+            if (SX[i] != 0) {
+                const S dl = f[i] - ld(i, -1, 0), dr = ld(i, 1, 0) - f[i];
+                const S M = minmod(dr, dl);
+                const S cx = stage_coef_x<S, HALF>(K, i, z);
+                if (SX[i] > 0) adv = cx * (dl + S(0.5) * (M - from_left(M)));
+                else adv = cx * (dr - S(0.5) * (from_right(M) - M));
+            }
+        } else if (SX[i] > 0)
             adv = stage_coef_x<S, HALF>(K, i, z) *
                   nnd_pos<S>(ld(i, -2, 0), ld(i, -1, 0), f[i], ld(i, 1, 0));
         else if (SX[i] < 0)

@@ -12,8 +12,10 @@
 //   address computation every other velocity.
 // A row of f^n is fetched from HBM as 16 contiguous 512-byte segments (one
 // per velocity), and stage 1 is recomputed on 4 halo columns for 120 outputs.
-// Wave (r, h) of a row r handles columns [64h, 64h + 64) of the strip's
-// stage-1 and stage-2 windows.  The global loads of the next rows are issued
+// Wave (r, h) of a row r computes columns [62h - 1, 62h + 63) of the
+// strip's stage-1 and stage-2 windows and keeps its lanes 1 .. 62: the
+// x-direction NND takes the neighbouring cells' minmod terms from the
+// neighbouring lanes (stage_cell_k with XLANE).  The global loads of the next rows are issued
 // in two halves, before stage 1 and before stage 2, and each lane stores its
 // own stage-2 cell: spreading the memory instructions over the iteration
 // keeps waves from stalling on a full memory queue.
@@ -55,7 +57,13 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int rw = wave >> 1;                     // row of the iteration, uniform
     const int h = wave & 1;                       // half of the row, uniform
-    const int col = 64 * h + lane;                // column of this lane in the stage windows
+    const int col = 64 * h + lane;                // column of this lane in the F0 row (loads)
+    // Column of this lane in the stage windows.  The x-direction NND shares
+    // minmod terms between neighbouring lanes, so the first and last lane of
+    // each wave only serve their neighbours: wave h computes columns
+    // 62h - 1 .. 62h + 62 and keeps lanes 1 .. 62.
+    const int ccol = 62 * h - 1 + lane;
+    const bool keep = lane >= 1 && lane <= 62;
     const int nx = K.nx, ny = K.ny, bcx = K.bcx, bcy = K.bcy;
     const int64_t cells = (int64_t)nx * ny;
     const int nrows = yb - ya;
@@ -127,23 +135,25 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
         if (t < t_end) issue_loads(t + 1, 0);
         lds_barrier();
 
-        // stage 1: f^(1) at row q1, column x0 - 2 + col
+        // stage 1: f^(1) at row q1, column x0 - 2 + ccol
         const int q1 = 2 + (t - 2) * R + rw;
         if (q1 >= -2 && q1 < nrows + 2) {
             RingLd<S, W0> ld;
             ld.ring = F0;
-            const int x1 = x0 - 2 + col;
+            const int x1 = x0 - 2 + ccol;
 #pragma unroll
             for (int o = -2; o <= 2; ++o) {
                 ld.slot[o + 2] = slot(q1 + o);
                 const int c = (bcx == CDBM_ZERO_GRADIENT) ? min(max(x1 + o, 0), nx - 1) - (x0 - 4)
-                                                          : col + 2 + o;
-                ld.col[o + 2] = min(c, W0 - 1);   // lanes past the window read in bounds
+                                                          : ccol + 2 + o;
+                ld.col[o + 2] = min(max(c, 0), W0 - 1);   // discarded lanes read in bounds
             }
             S out[NV];
-            stage_cell_k<S, false>(ld, K, out);
-            if (col < W1) {
-                S* dst = F1 + slot(q1) * NV * W1 + col;
+            stage_cell_k<S, false, RingLd<S, W0>, true>(ld, K, out);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) materialize(out[i]);
+            if (keep && ccol < TX + 4) {
+                S* dst = F1 + slot(q1) * NV * W1 + ccol;
 #pragma unroll
                 for (int i = 0; i < NV; ++i) dst[i * W1] = out[i];
             }
@@ -151,11 +161,11 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
         lds_barrier();
 
         if (t < t_end) issue_loads(t + 1, 1);
-        // stage 2: f^{n+1} at row q2, column x0 + col
+        // stage 2: f^{n+1} at row q2, column x0 + ccol
         const int q2 = (t - 2) * R + rw;
         if (q2 >= 0 && q2 < nrows) {
             const int r2 = ya + q2;
-            const int x = x0 + col;
+            const int x = x0 + ccol;
             RingLd<S, W1> ld;
             ld.ring = F1;
 #pragma unroll
@@ -166,9 +176,11 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
                 ld.col[o + 2] = min(max(cc - (x0 - 2), 0), W1 - 1);
             }
             S out[NV];
-            stage_cell_k<S, true>(ld, K, out);
-            if (col < TX && x < nx) {
-                const S* fn = F0 + slot(q2) * NV * W0 + 4 + col;   // f^n of the cell
+            stage_cell_k<S, true, RingLd<S, W1>, true>(ld, K, out);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) materialize(out[i]);
+            if (keep && ccol < TX && x < nx) {
+                const S* fn = F0 + slot(q2) * NV * W0 + 4 + ccol;   // f^n of the cell
                 S* dst = fout + (int64_t)r2 * nx + x;
 #pragma unroll
                 for (int i = 0; i < NV; ++i) dst[(int64_t)i * cells] = fma(S(0.5), fn[i * W0], out[i]);
