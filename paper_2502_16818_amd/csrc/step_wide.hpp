@@ -127,16 +127,22 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
 
     const int t0 = 2 - (8 + R - 1) / R;          // first iteration whose loads reach row -4
     const int t_end = (nrows + R - 1) / R + 1;   // last iteration with a stage-2 row
+    // Iteration t runs stage 1 (phase A), then stores the f^n rows that
+    // stage 1 of t + 1 needs and runs stage 2 (phase B): two barriers per
+    // iteration.  The F0 slots that phase B refills held the rows of this
+    // iteration's stage-2 cells, so stage 1 reads those cells' f^n (the Heun
+    // term) into registers first.
     issue_loads(t0, 0);
     issue_loads(t0, 1);
+    store_loads(t0);
+    issue_loads(t0 + 1, 0);
+    lds_barrier();   // the previous segment of this block is done with the rings
+    S fn2[NV];       // f^n of this lane's stage-2 cell
     for (int t = t0; t <= t_end; ++t) {
-        lds_barrier();   // the stages of iteration t-1 are done with the slots reused below
-        store_loads(t);
-        if (t < t_end) issue_loads(t + 1, 0);
-        lds_barrier();
-
-        // stage 1: f^(1) at row q1, column x0 - 2 + ccol
+        if (t < t_end) issue_loads(t + 1, 1);
+        // phase A, stage 1: f^(1) at row q1, column x0 - 2 + ccol
         const int q1 = 2 + (t - 2) * R + rw;
+        const int q2 = q1 - 2;   // stage-2 row of this iteration
         if (q1 >= -2 && q1 < nrows + 2) {
             RingLd<S, W0> ld;
             ld.ring = F0;
@@ -157,12 +163,20 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
 #pragma unroll
                 for (int i = 0; i < NV; ++i) dst[i * W1] = out[i];
             }
+            if (q2 >= 0 && q2 < nrows) {
+                const S* fn = F0 + slot(q2) * NV * W0 + min(4 + ccol, W0 - 1);
+#pragma unroll
+                for (int i = 0; i < NV; ++i) fn2[i] = fn[i * W0];
+            }
         }
         lds_barrier();
 
-        if (t < t_end) issue_loads(t + 1, 1);
+        // phase B: f^n rows for stage 1 of t + 1, then stage 2
+        if (t < t_end) {
+            store_loads(t + 1);
+            if (t + 1 < t_end) issue_loads(t + 2, 0);
+        }
         // stage 2: f^{n+1} at row q2, column x0 + ccol
-        const int q2 = (t - 2) * R + rw;
         if (q2 >= 0 && q2 < nrows) {
             const int r2 = ya + q2;
             const int x = x0 + ccol;
@@ -180,14 +194,13 @@ __device__ __forceinline__ void fused_strip_w(const float* __restrict__ fin,
 #pragma unroll
             for (int i = 0; i < NV; ++i) materialize(out[i]);
             if (keep && ccol < TX && x < nx) {
-                const S* fn = F0 + slot(q2) * NV * W0 + 4 + ccol;   // f^n of the cell
                 S* dst = fout + (int64_t)r2 * nx + x;
 #pragma unroll
-                for (int i = 0; i < NV; ++i) dst[(int64_t)i * cells] = fma(S(0.5), fn[i * W0], out[i]);
+                for (int i = 0; i < NV; ++i) dst[(int64_t)i * cells] = fma(S(0.5), fn2[i], out[i]);
             }
         }
+        lds_barrier();   // stage 1 of t + 1 overwrites F1 slots read above
     }
-    lds_barrier();
 }
 
 }  // namespace cdbm
