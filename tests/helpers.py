@@ -97,3 +97,24 @@ def check_patch_step(run, f_prev, f_next, cells, precision, tol=None):
         worst = max(worst, err)
         assert err <= tol, (x, y, err)
     return worst
+
+
+def check_column_step(run, f_prev, f_next, x, precision, tol=None):
+    """Compare the whole column x of f_next (every row) with the oracle's step
+    of the 9-column, full-height strip of f_prev around it (periodic in y, so
+    the strip's only boundary is 4 columns away); returns the worst relative
+    error, max |difference| / max |f| of the strip.  Every row seam of any
+    assignment of rows to blocks lies on the column."""
+    tol = FP64_MIXED_PATCH_TOL[precision] if tol is None else tol
+    p0 = C.Params.from_run(run)
+    cols, _, cx, _, bcx = patch_indices(run, x, 0)
+    ci = torch.as_tensor(cols, device=f_prev.device)
+    fp = f_prev.index_select(2, ci).double().cpu()
+    p = C.Params(len(cols), run.ny, p0.dx, p0.dy, p0.dt, p0.tau, p0.I, p0.v, p0.eta,
+                 bcx, C.PERIODIC)
+    want = C.step(fp, p)[:, :, cx]
+    got = f_next[:, :, x].double().cpu()
+    diff = (got - want).abs().amax(dim=0)
+    err = float(diff.max() / fp.abs().max())
+    assert err <= tol, (x, int(diff.argmax()), err)
+    return err

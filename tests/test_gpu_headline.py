@@ -12,13 +12,16 @@ cover both x sides, the strip seams (every 120 columns in the mixed form,
 every 56 in FP64), the seams of the
 row pieces of any piece count up to 8, the periodic y wrap, and random
 cells; both precision forms, two consecutive steps (from the equilibrium
-start, then from a state with non-equilibrium parts)."""
+start, then from a state with non-equilibrium parts).  Whole columns (every
+row, against the oracle's step of the 9-column strip around them) cover the
+row seams of whatever pieces and tails the launch assigns to blocks."""
 import numpy as np
 import pytest
 import torch
 
 import workloads as W
 from oracle import cdbm as C
+from helpers import check_column_step as _check_column
 from helpers import check_patch_step as _check_step
 
 FP64, MIXED = 0, 1
@@ -40,6 +43,24 @@ def _sample_cells(nx, ny, rng):
     cells += [(int(rng.integers(0, nx)), int(rng.integers(0, ny))) for _ in range(24)]
     cells += [(0, 0), (nx - 1, ny - 1), (0, ny - 1), (nx - 1, 0)]
     return cells
+
+
+# Columns checked over their full height: inside the first strip, at a strip
+# seam of each form, and at both zero-gradient sides.
+FULL_COLUMNS = (0, 60, 2039, 2040, 4095)
+
+
+def test_column_step_equals_full_grid_step():
+    """The column check itself (CPU): on a small grid of the same setup, the
+    oracle's step on the 9-column strip reproduces its full-grid step on the
+    strip's centre column, at the zero-gradient sides and inside."""
+    run = W.lax_acoustic_2d(40, ny=24, seed=3)
+    p = C.Params.from_run(run)
+    f0 = C.initial_distribution(run.rho, run.ux, run.uy, run.T, p)
+    f0 = f0 * (1 + 1e-3 * torch.sin(torch.arange(f0.numel(), dtype=f0.dtype)).reshape(f0.shape))
+    f1 = C.step(f0, p)
+    for x in (0, 2, 4, 17, 35, 39):
+        assert _check_column(run, f0, f1, x, FP64, tol=1e-14) <= 1e-14
 
 
 def test_patch_step_equals_full_grid_step():
@@ -71,6 +92,9 @@ def test_headline_full_size_sampled_cells_match_oracle(precision):
     e1 = _check_step(run, f0, f1, cells, precision)
     e2 = _check_step(run, f1, f2, cells, precision)
     print(f"  {len(cells)} cells: worst relative error step 1 {e1:.2e}, step 2 {e2:.2e}")
+    c1 = max(_check_column(run, f0, f1, x, precision) for x in FULL_COLUMNS)
+    c2 = max(_check_column(run, f1, f2, x, precision) for x in FULL_COLUMNS)
+    print(f"  {len(FULL_COLUMNS)} full columns: step 1 {c1:.2e}, step 2 {c2:.2e}")
     s.close()
 
 
@@ -97,5 +121,6 @@ def test_largest_grids_sampled_cells_match_oracle(precision, nx, ny):
     f1 = s.step(f0)
     torch.cuda.synchronize()
     e = _check_step(run, f0, f1, cells, precision)
-    print(f"  {len(cells)} cells: worst relative error {e:.2e}")
+    c = max(_check_column(run, f0, f1, x, precision) for x in (1, 120, nx - 2))
+    print(f"  {len(cells)} cells: worst relative error {e:.2e}; 3 full columns {c:.2e}")
     s.close()
