@@ -36,7 +36,9 @@ __global__ void __launch_bounds__(StripKernel<S>::NT) k_step_fused(const S* __re
     __shared__ __attribute__((aligned(16))) S F1[SK::F1_ELEMS];
     const KParams& K = *Kd;
     const int nstrips = (K.nx + SK::TX - 1) / SK::TX;
-    if (pieces > 0) {
+    // (the launch gives FP64 the persistent grid only; its kernel carries no
+    // piece code, which would cost it scalar registers)
+    if (sizeof(S) == 4 && pieces > 0) {
         // blocks go to the 8 XCDs round-robin; number them XCD by XCD so that
         // the blocks of one XCD take consecutive strips of the same rows and
         // share the halo columns in that XCD's L2
