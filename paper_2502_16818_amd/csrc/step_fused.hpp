@@ -95,6 +95,7 @@ struct RingLd {
 // arithmetic feeding them into that branch, apart from the lane shifts
 // below, which must run in every lane.
 __device__ __forceinline__ void materialize(float& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void materialize(double& v) { asm volatile("" : "+v"(v)); }
 
 // Value of a 32-bit register in lane - 1 (from_left) or lane + 1
 // (from_right) of the wave: DPP whole-wave shifts, which the compiler folds
@@ -106,6 +107,17 @@ __device__ __forceinline__ float from_left(float v) {
 __device__ __forceinline__ float from_right(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
+// 64-bit values move as two 32-bit halves (two shifts).
+template <int CTRL>
+__device__ __forceinline__ double shift_lanes(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double from_left(double v) { return shift_lanes<0x138>(v); }
+__device__ __forceinline__ double from_right(double v) { return shift_lanes<0x130>(v); }
 
 // One stage at one cell with every run constant read from K at an opaque
 // zero offset (see opaque_zero).  First stage (HALF = false): returns
@@ -113,7 +125,7 @@ __device__ __forceinline__ float from_right(float v) {
 // the 1/2 folded into the coefficients, so that the Heun combination is
 // f^n / 2 plus the result.
 //
-// XLANE (FP32 only): the lanes of the wave hold consecutive cells of a row,
+// XLANE: the lanes of the wave hold consecutive cells of a row,
 // and the x-direction NND takes the minmod of the neighbouring cell from the
 // neighbouring lane.  Each lane forms M = minmod(f_{j+1} - f_j, f_j - f_{j-1});
 // the positive-velocity difference needs M of lane j - 1 and the negative one
@@ -122,7 +134,6 @@ __device__ __forceinline__ float from_right(float v) {
 // results are bitwise those of the per-lane form.  All 64 lanes must run it.
 template <typename S, bool HALF, class Ld, bool XLANE = false>
 __device__ __forceinline__ void stage_cell_k(const Ld& ld, const KParams& K, S out[NV]) {
-    static_assert(!XLANE || sizeof(S) == 4, "lane shifts move 32-bit values");
     const int z = opaque_zero();
     S f[NV];
     double fd[NV];
@@ -247,6 +258,13 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // 0..R-1, uniform
+    // Column of this lane in the stage windows: the x-direction NND shares
+    // minmod terms between neighbouring lanes (stage_cell_k with XLANE), so
+    // lane 0 and lane 63 only serve their neighbours; lane l computes column
+    // l - 1 and lanes 1 .. 62 are kept (60 stage-1 and 56 stage-2 columns
+    // are needed).
+    const int ccol = lane - 1;
+    const bool keep = lane >= 1 && lane <= 62;
     const int nx = K.nx, ny = K.ny, bcx = K.bcx, bcy = K.bcy;
     const int64_t cells = (int64_t)nx * ny;
     const int nrows = yb - ya;
@@ -327,33 +345,37 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
         if (t < t_end) issue_loads(t + 1, 0);
         lds_barrier();
 
-        // stage 1: f^(1) at row q1, column x0 - 2 + lane
+        // stage 1: f^(1) at row q1, column x0 - 2 + ccol
         const int q1 = 2 + (t - 2) * R + wave;
         if (q1 >= -2 && q1 < nrows + 2) {
             RingLd<S, W0> ld;
             ld.ring = F0;
-            const int x1 = x0 - 2 + lane;
+            const int x1 = x0 - 2 + ccol;
 #pragma unroll
             for (int o = -2; o <= 2; ++o) {
                 ld.slot[o + 2] = slot(q1 + o);
                 const int c = (bcx == CDBM_ZERO_GRADIENT) ? min(max(x1 + o, 0), nx - 1) - (x0 - 4)
-                                                          : lane + 2 + o;
-                ld.col[o + 2] = min(c, W0 - 1);   // lanes past the window read in bounds
+                                                          : ccol + 2 + o;
+                ld.col[o + 2] = min(max(c, 0), W0 - 1);   // discarded lanes read in bounds
             }
             S out[NV];
-            stage_cell_k<S, false>(ld, K, out);
-            S* dst = F1 + slot(q1) * NV * W1 + lane;
+            stage_cell_k<S, false, RingLd<S, W0>, true>(ld, K, out);
 #pragma unroll
-            for (int i = 0; i < NV; ++i) dst[i * W1] = out[i];
+            for (int i = 0; i < NV; ++i) materialize(out[i]);
+            if (keep && ccol < TX + 4) {
+                S* dst = F1 + slot(q1) * NV * W1 + ccol;
+#pragma unroll
+                for (int i = 0; i < NV; ++i) dst[i * W1] = out[i];
+            }
         }
         lds_barrier();
 
         if (t < t_end) issue_loads(t + 1, 1);
-        // stage 2: f^{n+1} at row q2, column x0 + lane
+        // stage 2: f^{n+1} at row q2, column x0 + ccol
         const int q2 = (t - 2) * R + wave;
         if (q2 >= 0 && q2 < nrows) {
             const int r2 = ya + q2;
-            const int x = x0 + lane;
+            const int x = x0 + ccol;
             RingLd<S, W1> ld;
             ld.ring = F1;
 #pragma unroll
@@ -364,9 +386,11 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
                 ld.col[o + 2] = min(max(cc - (x0 - 2), 0), W1 - 1);
             }
             S out[NV];
-            stage_cell_k<S, true>(ld, K, out);
-            if (lane < TX && x < nx) {
-                const S* fn = F0 + slot(q2) * NV * W0 + 4 + lane;   // f^n of the cell
+            stage_cell_k<S, true, RingLd<S, W1>, true>(ld, K, out);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) materialize(out[i]);
+            if (keep && ccol < TX && x < nx) {
+                const S* fn = F0 + slot(q2) * NV * W0 + 4 + ccol;   // f^n of the cell
                 S* dst = fout + (int64_t)r2 * nx + x;
 #pragma unroll
                 for (int i = 0; i < NV; ++i) dst[(int64_t)i * cells] = fma(S(0.5), fn[i * W0], out[i]);
