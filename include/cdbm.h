@@ -158,6 +158,26 @@ int cdbm_conserved_totals(cdbm_handle* h, const void* f, double* out4, void* str
 int cdbm_step_adjoint(cdbm_handle* h, const void* f_n, const void* lam_np1, void* lam_n,
                       double* dL_dtau, void* stream);
 
+/* One time step (cdbm_step with nsteps = 1) that also keeps its first
+ * Runge-Kutta stage (Sec. 2: the second-order Runge-Kutta scheme in time;
+ * with Eq. (1) and the NND derivative of Eqs. (12)-(20) as L):
+ * f1_out = f_in + dt L(f_in) and f_out = f_in / 2 + (f1_out + dt L(f1_out)) / 2,
+ * as two single-stage launches whatever the handle's step form.  f_in, f1_out,
+ * f_out: device [16][ny][nx] in the handle's precision, pairwise
+ * non-overlapping.  f_out equals what cdbm_step gives for one step bit for
+ * bit.  Meant for reverse passes that keep the stages of recomputed steps
+ * (see cdbm_step_adjoint_stage). */
+int cdbm_step_keep_stage(cdbm_handle* h, const void* f_in, void* f1_out, void* f_out,
+                         void* stream);
+
+/* cdbm_step_adjoint with the first Runge-Kutta stage of the step supplied
+ * instead of recomputed: f1 = f_n + dt L(f_n) (device [16][ny][nx], handle's
+ * precision), as cdbm_step_keep_stage writes it.  Same arguments, contract
+ * and results as cdbm_step_adjoint (bit for bit when f1 is that stage);
+ * lam_n must not overlap f1 either.  Saves one single-stage launch. */
+int cdbm_step_adjoint_stage(cdbm_handle* h, const void* f_n, const void* f1,
+                            const void* lam_np1, void* lam_n, double* dL_dtau, void* stream);
+
 /* Reverse-mode product of cdbm_init: g_q = (d f^eq(q) / d q)^T lam_f0 for
  * q = (rho, u_x, u_y, T) taken from the given fields (device double [ny][nx]).
  * lam_f0: device double [16][ny][nx].  Outputs overwritten. */

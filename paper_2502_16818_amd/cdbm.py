@@ -24,6 +24,7 @@ STEP_AUTO, STEP_FUSED, STEP_SPLIT = 0, 1, 2
 EXPORTS = (
     "cdbm_last_error", "cdbm_create", "cdbm_destroy", "cdbm_get_params", "cdbm_init",
     "cdbm_step", "cdbm_moments", "cdbm_tne", "cdbm_conserved_totals", "cdbm_step_adjoint",
+    "cdbm_step_keep_stage", "cdbm_step_adjoint_stage",
     "cdbm_init_adjoint", "cdbm_moments_adjoint", "cdbm_batch_create", "cdbm_batch_destroy",
     "cdbm_batch_init", "cdbm_batch_step",
 )
@@ -71,6 +72,8 @@ def load() -> ctypes.CDLL:
         "cdbm_tne": ([_vp, _vp, _vp, _vp], _i32),
         "cdbm_conserved_totals": ([_vp, _vp, _vp, _vp], _i32),
         "cdbm_step_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp], _i32),
+        "cdbm_step_keep_stage": ([_vp, _vp, _vp, _vp, _vp], _i32),
+        "cdbm_step_adjoint_stage": ([_vp] * 7, _i32),
         "cdbm_init_adjoint": ([_vp] * 11, _i32),
         "cdbm_moments_adjoint": ([_vp] * 8, _i32),
         "cdbm_batch_create": ([P, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_vp)], _i32),
@@ -196,6 +199,16 @@ class Solver:
                "cdbm_step")
         return f_out
 
+    def step_keep_stage(self, f_in: torch.Tensor, f1_out: Optional[torch.Tensor] = None,
+                        f_out: Optional[torch.Tensor] = None):
+        """One step that also returns its first Runge-Kutta stage f_in + dt L(f_in):
+        (f1_out, f_out)."""
+        f1_out = self.empty_f() if f1_out is None else f1_out
+        f_out = self.empty_f() if f_out is None else f_out
+        _check(load().cdbm_step_keep_stage(self._h, self._f(f_in), self._f(f1_out),
+                                           self._f(f_out), _stream()), "cdbm_step_keep_stage")
+        return f1_out, f_out
+
     def moments(self, f: torch.Tensor) -> Tuple[torch.Tensor, ...]:
         outs = [self.empty_field() for _ in range(4)]
         _check(load().cdbm_moments(self._h, self._f(f), *[_ptr(o) for o in outs], _stream()),
@@ -219,12 +232,21 @@ class Solver:
 
     def step_adjoint(self, f_n: torch.Tensor, lam_np1: torch.Tensor,
                      lam_n: Optional[torch.Tensor] = None,
-                     dtau: Optional[torch.Tensor] = None):
+                     dtau: Optional[torch.Tensor] = None,
+                     f1: Optional[torch.Tensor] = None):
+        """Transpose of one step; f1, if given, is the step's first stage (as
+        step_keep_stage returns it) and saves its recomputation."""
         lam_n = self.empty_lam() if lam_n is None else lam_n
         dtau = torch.zeros(1, dtype=torch.float64, device="cuda") if dtau is None else dtau
-        _check(load().cdbm_step_adjoint(self._h, self._f(f_n), self._lam(lam_np1), self._lam(lam_n),
-                                        _ptr(dtau, torch.float64, 1), _stream()),
-               "cdbm_step_adjoint")
+        if f1 is None:
+            _check(load().cdbm_step_adjoint(self._h, self._f(f_n), self._lam(lam_np1),
+                                            self._lam(lam_n), _ptr(dtau, torch.float64, 1),
+                                            _stream()), "cdbm_step_adjoint")
+        else:
+            _check(load().cdbm_step_adjoint_stage(self._h, self._f(f_n), self._f(f1),
+                                                  self._lam(lam_np1), self._lam(lam_n),
+                                                  _ptr(dtau, torch.float64, 1), _stream()),
+                   "cdbm_step_adjoint_stage")
         return lam_n, dtau
 
     def init_adjoint(self, rho, ux, uy, T, lam_f0: torch.Tensor):

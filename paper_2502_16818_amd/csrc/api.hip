@@ -276,6 +276,26 @@ int cdbm_step(cdbm_handle* h, const void* f_in, void* f_out, int32_t nsteps, voi
     return run_steps(step_single, h, f_in, f_out, h->scratch, nsteps, st, h->graph);
 }
 
+int cdbm_step_keep_stage(cdbm_handle* h, const void* f_in, void* f1_out, void* f_out,
+                         void* stream) {
+    if (!h || !f_in || !f1_out || !f_out) return fail(CDBM_EINVAL, "null argument");
+    const char* a = (const char*)f_in;
+    const char* b = (const char*)f1_out;
+    const char* c = (const char*)f_out;
+    const size_t n = h->fbytes;
+    if ((a < b + n && b < a + n) || (a < c + n && c < a + n) || (b < c + n && c < b + n))
+        return fail(CDBM_EINVAL, "f_in, f1_out and f_out must not overlap");
+    int rc = check_device(h);
+    if (rc != CDBM_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = mixed(h) ? launch_stage<float>(f_in, nullptr, f1_out, false, h->k, h->kdev, st)
+                            : launch_stage<double>(f_in, nullptr, f1_out, false, h->k, h->kdev, st);
+    if (e == hipSuccess)
+        e = mixed(h) ? launch_stage<float>(f1_out, f_in, f_out, true, h->k, h->kdev, st)
+                     : launch_stage<double>(f1_out, f_in, f_out, true, h->k, h->kdev, st);
+    return e == hipSuccess ? CDBM_OK : hip_fail(e, "stage launch");
+}
+
 int cdbm_moments(cdbm_handle* h, const void* f, double* rho, double* ux, double* uy, double* T,
                  void* stream) {
     if (!h || !f || !rho || !ux || !uy || !T) return fail(CDBM_EINVAL, "null argument");

@@ -6,7 +6,8 @@
 //   lam^n = lam' / 2 + E'(f)^T mu
 //   dL/dtau += lam' . dE/dtau(f1) / 2 + mu . dE/dtau(f)
 // f1 is recomputed from f (the unfused stage kernel) into the handle's stage
-// buffer; mu lives in a second handle-owned buffer.  The two stage adjoints
+// buffer, or supplied by the caller (cdbm_step_adjoint_stage); mu lives in a
+// second handle-owned buffer.  The two stage adjoints
 // leave their per-block tau partials side by side, summed by one launch.  Adjoint vectors are
 // double in both precision forms: for a loss of the density alone lam_i is
 // close to one value for all i, and the gradient with respect to u and T is
@@ -21,14 +22,20 @@ using namespace cdbm;
 
 namespace {
 
+// f1: the first stage of the step, or nullptr to recompute it into the
+// handle's stage buffer.
 template <typename S>
-int step_adjoint_impl(cdbm_handle* h, const void* f_n, const void* lam_np1, void* lam_n,
-                      double* dtau, hipStream_t st) {
+int step_adjoint_impl(cdbm_handle* h, const void* f_n, const void* f1, const void* lam_np1,
+                      void* lam_n, double* dtau, hipStream_t st) {
     const KParams& K = h->k;
     const int nb = stage_adjoint_blocks(K);
-    hipError_t e = launch_stage<S>(f_n, nullptr, h->stage, false, K, h->kdev, st);
-    if (e != hipSuccess) return hip_fail(e, "stage recompute launch");
-    e = launch_stage_adjoint<S>(h->stage, lam_np1, nullptr, h->lam_mid, h->tau_part, 0.5, 0.0, K, st);
+    hipError_t e = hipSuccess;
+    if (!f1) {
+        e = launch_stage<S>(f_n, nullptr, h->stage, false, K, h->kdev, st);
+        if (e != hipSuccess) return hip_fail(e, "stage recompute launch");
+        f1 = h->stage;
+    }
+    e = launch_stage_adjoint<S>(f1, lam_np1, nullptr, h->lam_mid, h->tau_part, 0.5, 0.0, K, st);
     if (e != hipSuccess) return hip_fail(e, "stage adjoint launch");
     e = launch_stage_adjoint<S>(f_n, h->lam_mid, lam_np1, lam_n, h->tau_part + nb, 1.0, 0.5, K, st);
     if (e != hipSuccess) return hip_fail(e, "stage adjoint launch");
@@ -45,6 +52,27 @@ bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
     return x < y + bn && y < x + an;
 }
 
+// Checks and buffers shared by both step adjoints (f1 may be nullptr).
+int step_adjoint_entry(cdbm_handle* h, const void* f_n, const void* f1, const void* lam_np1,
+                       void* lam_n, double* dL_dtau, void* stream) {
+    const size_t lbytes = sizeof(double) * (size_t)NV * (size_t)h->cells;
+    if (overlaps(lam_n, lbytes, f_n, h->fbytes) || overlaps(lam_n, lbytes, lam_np1, lbytes))
+        return fail(CDBM_EINVAL, "lam_n overlaps f_n or lam_np1");
+    if (f1 && overlaps(lam_n, lbytes, f1, h->fbytes))
+        return fail(CDBM_EINVAL, "lam_n overlaps f1");
+    int rc = check_device(h);
+    if (rc != CDBM_OK) return rc;
+    if (!f1 && (rc = ensure_buffer(h, &h->stage)) != CDBM_OK) return rc;
+    if (!h->lam_mid &&
+        hipMalloc(&h->lam_mid, sizeof(double) * (size_t)NV * (size_t)h->cells) != hipSuccess) {
+        h->lam_mid = nullptr;
+        return fail(CDBM_ENOMEM, "hipMalloc of the adjoint buffer failed");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    return mixed(h) ? step_adjoint_impl<float>(h, f_n, f1, lam_np1, lam_n, dL_dtau, st)
+                    : step_adjoint_impl<double>(h, f_n, f1, lam_np1, lam_n, dL_dtau, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -52,20 +80,14 @@ extern "C" {
 int cdbm_step_adjoint(cdbm_handle* h, const void* f_n, const void* lam_np1, void* lam_n,
                       double* dL_dtau, void* stream) {
     if (!h || !f_n || !lam_np1 || !lam_n || !dL_dtau) return fail(CDBM_EINVAL, "null argument");
-    const size_t lbytes = sizeof(double) * (size_t)NV * (size_t)h->cells;
-    if (overlaps(lam_n, lbytes, f_n, h->fbytes) || overlaps(lam_n, lbytes, lam_np1, lbytes))
-        return fail(CDBM_EINVAL, "lam_n overlaps f_n or lam_np1");
-    int rc = check_device(h);
-    if (rc != CDBM_OK) return rc;
-    if ((rc = ensure_buffer(h, &h->stage)) != CDBM_OK) return rc;
-    if (!h->lam_mid &&
-        hipMalloc(&h->lam_mid, sizeof(double) * (size_t)NV * (size_t)h->cells) != hipSuccess) {
-        h->lam_mid = nullptr;
-        return fail(CDBM_ENOMEM, "hipMalloc of the adjoint buffer failed");
-    }
-    hipStream_t st = (hipStream_t)stream;
-    return mixed(h) ? step_adjoint_impl<float>(h, f_n, lam_np1, lam_n, dL_dtau, st)
-                    : step_adjoint_impl<double>(h, f_n, lam_np1, lam_n, dL_dtau, st);
+    return step_adjoint_entry(h, f_n, nullptr, lam_np1, lam_n, dL_dtau, stream);
+}
+
+int cdbm_step_adjoint_stage(cdbm_handle* h, const void* f_n, const void* f1,
+                            const void* lam_np1, void* lam_n, double* dL_dtau, void* stream) {
+    if (!h || !f_n || !f1 || !lam_np1 || !lam_n || !dL_dtau)
+        return fail(CDBM_EINVAL, "null argument");
+    return step_adjoint_entry(h, f_n, f1, lam_np1, lam_n, dL_dtau, stream);
 }
 
 int cdbm_init_adjoint(cdbm_handle* h, const double* rho, const double* ux, const double* uy,

@@ -7,7 +7,10 @@ entry points: the moments adjoint seeds dL/df at the final step, every step
 is transposed with cdbm_step_adjoint (which also accumulates dL/dtau), and
 the initial-equilibrium adjoint maps dL/df0 to the initial fields.  Forward
 states are checkpointed every `every` steps; the backward pass recomputes
-the states of one segment at a time from its checkpoint.
+the states of one segment at a time from its checkpoint, and, while a
+segment's first Runge-Kutta stages fit in KEEP_STAGE_BYTES, keeps them
+(cdbm_step_keep_stage) so that the step adjoints need not recompute them
+(cdbm_step_adjoint_stage; the gradients are the same bit for bit).
 """
 from __future__ import annotations
 
@@ -17,6 +20,10 @@ from typing import Optional
 import torch
 
 from .cdbm import MIXED, Solver
+
+# Device memory the backward pass may spend on the first stages of one
+# segment's recomputed steps (one f per step).
+KEEP_STAGE_BYTES = 8 << 30
 
 
 def _segments(nsteps: int, every: int):
@@ -63,13 +70,22 @@ class CDBMRollout(torch.autograd.Function):
         lam_next = s.empty_lam()
         dtau = torch.zeros(1, dtype=torch.float64, device="cuda")
         segs = _segments(ctx.nsteps, ctx.every)
-        states = [s.empty_f() for _ in range(min(ctx.every, ctx.nsteps))]
+        nmax = min(ctx.every, ctx.nsteps)
+        states = [s.empty_f() for _ in range(nmax)]
+        fbytes = states[0].numel() * states[0].element_size()
+        keep = nmax * fbytes <= KEEP_STAGE_BYTES
+        stages = [s.empty_f() for _ in range(nmax)] if keep else None
+        spare = s.empty_f() if keep else None   # state after a segment's last step, unused
         for (k0, n), ck in zip(reversed(segs), reversed(ctx.ckpts)):
             states[0].copy_(ck)
-            for j in range(1, n):
-                s.step(states[j - 1], states[j], nsteps=1)
+            if keep:
+                for j in range(n):
+                    s.step_keep_stage(states[j], stages[j], states[j + 1] if j + 1 < n else spare)
+            else:
+                for j in range(1, n):
+                    s.step(states[j - 1], states[j], nsteps=1)
             for j in reversed(range(n)):
-                s.step_adjoint(states[j], lam, lam_next, dtau)
+                s.step_adjoint(states[j], lam, lam_next, dtau, f1=stages[j] if keep else None)
                 lam, lam_next = lam_next, lam
         rho0, ux0, uy0, T0 = ctx.saved_tensors
         g0 = s.init_adjoint(rho0, ux0, uy0, T0, lam)

@@ -94,6 +94,8 @@ def test_null_arguments_are_rejected(lib):
     h = ctypes.c_void_p()
     assert lib.cdbm_create(None, ctypes.byref(h)) == -1
     assert lib.cdbm_step(None, None, None, 1, None) == -1
+    assert lib.cdbm_step_keep_stage(None, None, None, None, None) == -1
+    assert lib.cdbm_step_adjoint_stage(None, None, None, None, None, None, None) == -1
     assert lib.cdbm_destroy(None) == 0
 
 

@@ -271,3 +271,61 @@ def test_gradient_workload_full_size():
             for a, b in zip(d32, d64):
                 assert abs(a - b) <= 1e-3 * abs(b)
             assert abs(t32 - t64) <= 1e-2 * abs(t64)
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("run", _cases()[:3], ids=lambda r: f"{r.name}_bc{r.bc_x}{r.bc_y}")
+def test_step_keep_stage_matches_step_and_oracle_stage(run, precision):
+    """cdbm_step_keep_stage: f_out is cdbm_step's one step bit for bit, and
+    f1_out is the first Runge-Kutta stage f + dt L(f) of the oracle."""
+    p, f = _state(run)
+    s = _solver(run, precision)
+    fin = _cuda(f, s.dtype)
+    f1, fout = s.step_keep_stage(fin)
+    ref = s.step(fin, nsteps=1)
+    torch.cuda.synchronize()
+    assert torch.equal(fout, ref)
+    fo = f.to(s.dtype).double()   # the oracle's stage from the same (rounded) state
+    want = fo + p.dt * C.rhs(fo, p)
+    err = rel_max(to_np(f1), want.numpy())
+    print(f"  stage rel err {err:.2e}")
+    assert err <= (1e-12 if precision == FP64 else 3e-7)
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("run", _cases(), ids=lambda r: f"{r.name}_bc{r.bc_x}{r.bc_y}")
+def test_step_adjoint_stage_equals_step_adjoint(run, precision):
+    """cdbm_step_adjoint_stage with the kept stage gives cdbm_step_adjoint's
+    lam_n and tau increment bit for bit."""
+    p, f = _state(run)
+    lam = torch.from_numpy(np.random.default_rng(10).standard_normal(f.shape))
+    s = _solver(run, precision)
+    fin = _cuda(f, s.dtype)
+    f1, _ = s.step_keep_stage(fin)
+    l_a, t_a = s.step_adjoint(fin, _cuda(lam))
+    l_b, t_b = s.step_adjoint(fin, _cuda(lam), f1=f1)
+    torch.cuda.synchronize()
+    assert torch.equal(l_a, l_b)
+    assert torch.equal(t_a, t_b)
+
+
+def test_rollout_gradients_equal_with_and_without_kept_stages(monkeypatch):
+    """The backward pass gives the same gradients bit for bit whether it keeps
+    the recomputed steps' first stages or lets the step adjoint recompute
+    them."""
+    from paper_2502_16818_amd import rollout as R
+    run = W.random_periodic(48, 40, seed=15, dt=2e-5, tau=1e-4)
+    target = torch.from_numpy(np.random.default_rng(16).uniform(0.9, 1.1, (run.ny, run.nx))).cuda()
+    grads = []
+    for cap in (R.KEEP_STAGE_BYTES, 0):
+        monkeypatch.setattr(R, "KEEP_STAGE_BYTES", cap)
+        s = _solver(run, MIXED)
+        g_in = [torch.tensor(a, dtype=torch.float64, device="cuda", requires_grad=True)
+                for a in (run.rho, run.ux, run.uy, run.T)]
+        tau = torch.tensor(run.tau, dtype=torch.float64, device="cuda", requires_grad=True)
+        rho, _, _, _ = R.rollout(s, *g_in, tau, 23, 10)
+        ((rho - target) ** 2).mean().backward()
+        grads.append([g.grad.clone() for g in g_in] + [tau.grad.clone()])
+        s.close()
+    for a, b in zip(*grads):
+        assert torch.equal(a, b)
