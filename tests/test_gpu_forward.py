@@ -1,5 +1,6 @@
 """Parity of the HIP forward path (init, fused step, moments, nonequilibrium,
 totals) with the FP64 oracle, through the C ABI."""
+import functools
 import sys
 
 import numpy as np
@@ -158,6 +159,41 @@ def test_fused_and_split_steps_are_bitwise_equal(precision):
             outs.append(s.step(f, nsteps=7))
             s.close()
         assert torch.equal(outs[0], outs[1]), run.name
+
+
+@functools.lru_cache(maxsize=1)
+def _piece_cases():
+    """Grids whose FP32 launch splits every strip into row pieces and gives
+    the strips' remaining rows (tails) to the compute units the pieces leave
+    idle, with one to five tails per unit (on 256 compute units), on both
+    row-movement forms and boundary kinds."""
+    out = []
+    for nx, ny, bc, tag in ((1001, 777, (0, 0), "percol"), (1000, 777, (1, 1), "zg"),
+                            (1536, 1536, (0, 0), "k2"), (2048, 2048, (1, 0), "k5"),
+                            (4096, 1000, (0, 1), "k4")):
+        r = W.random_periodic(nx, ny, seed=nx + ny, dt=2e-5, tau=2e-4)
+        r.bc_x, r.bc_y = bc
+        r.name = f"{r.name}_{tag}"
+        out.append(r)
+    return out
+
+
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_fused_pieces_and_tails_equal_split_steps(precision):
+    """Mid-size grids in the fused form (row pieces, strip tails on the spare
+    compute units, several segments per block) against the split form, which
+    reads every neighbour from HBM and has no pieces: bitwise equal over the
+    whole grid after three steps."""
+    for run in _piece_cases():
+        outs = []
+        for form in (FUSED, SPLIT):
+            s = _solver(run, precision, form)
+            f = s.init(run.rho, run.ux, run.uy, run.T)
+            outs.append(s.step(f, nsteps=3))
+            s.close()
+            del f
+        assert torch.equal(outs[0], outs[1]), run.name
+        del outs
 
 
 @pytest.mark.parametrize("form", sorted(FORMS))
