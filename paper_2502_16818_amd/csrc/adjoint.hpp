@@ -179,7 +179,12 @@ __device__ __forceinline__ double moments_vjp_k(const Macro& m, const KParams& K
 // no real cell exists).  Positions are local tile indices along one line;
 // the global index of a position only decides which gathers a
 // zero-gradient side skips.
-constexpr int ATX = 64, ATY = 4, AH = 3;
+// 32 x 4 cells: at 256 x 256, 512 blocks (two per compute unit) whose
+// halo-to-cell ratio (38 x 10 tile positions for 128 cells) still lets the
+// gathers come from L2; 64 x 4 (one block per compute unit) and 32 x 8
+// measured 6 % and 1 % slower per adjoint step, 64 x 2 and 32 x 2 (more halo)
+// 7 % and 20 % slower.
+constexpr int ATX = 32, ATY = 4, AH = 3;
 // Velocity groups of a stage-adjoint block: each group of ATX x ATY threads
 // takes every AG-th velocity, so a block keeps AG waves per 64 cells busy.
 constexpr int AG = 2;
