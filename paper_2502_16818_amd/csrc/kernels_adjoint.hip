@@ -194,7 +194,17 @@ __global__ void __launch_bounds__(256) k_accumulate(const double* __restrict__ p
                                                     double scale, double* __restrict__ dst) {
     __shared__ double red[256];
     double s = 0.0;
-    for (int b = threadIdx.x; b < n; b += blockDim.x) s += part[b];
+    int b = threadIdx.x;
+    // each thread's values in the order b, b + 256, ...; four loads in
+    // flight at a time instead of one
+    for (; b + 3 * 256 < n; b += 4 * 256) {
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = part[b + k * 256];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += v[k];
+    }
+    for (; b < n; b += 256) s += part[b];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
