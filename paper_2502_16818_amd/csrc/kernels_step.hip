@@ -36,9 +36,7 @@ __global__ void __launch_bounds__(StripKernel<S>::NT) k_step_fused(const S* __re
     __shared__ __attribute__((aligned(16))) S F1[SK::F1_ELEMS];
     const KParams& K = *Kd;
     const int nstrips = (K.nx + SK::TX - 1) / SK::TX;
-    // (the launch gives FP64 the persistent grid only; its kernel carries no
-    // piece code, which would cost it scalar registers)
-    if (sizeof(S) == 4 && pieces > 0) {
+    if (pieces > 0) {
         // blocks go to the 8 XCDs round-robin; number them XCD by XCD so that
         // the blocks of one XCD take consecutive strips of the same rows and
         // share the halo columns in that XCD's L2
@@ -75,7 +73,7 @@ struct Launch {
     int blocks, pieces, main_len;
 };
 
-// Grid of the step.  FP32: row-aligned pieces.  Plain form: P equal row
+// Grid of the step: row-aligned pieces.  Plain form: P equal row
 // pieces per strip, one block per (strip, piece), in as many rounds of one
 // block per compute unit as nstrips * P needs; P minimises rounds * (rows
 // per piece + FILL_ROWS), the time of the busiest compute unit with the
@@ -84,16 +82,17 @@ struct Launch {
 // one round with compute units to spare (nstrips * P < CUs): P pieces of L
 // rows per strip and the remaining T = ny - P L rows of each strip on the
 // spare units, k = ceil(nstrips / spare) tails on the busiest one; L
-// minimises max(L + FILL_ROWS, k (T + FILL_ROWS)) (4096 x 4096: 35 strips,
-// 7 pieces of 567 rows and 11 units taking 3 or 4 tails of 127 rows, against
-// 7 pieces of 586 rows and 11 idle units).  The launch takes the cheaper
-// form.  A persistent grid that splits the strip-major sequence of (strip,
-// row) evenly over the compute units balances the rows exactly but loses
-// the row alignment of neighbouring strips and their shared halo lines in
-// L2 (18 % slower at 4096 x 4096 in FP32); it serves grids too short for
-// pieces of 32 rows, and FP64, whose step is bound by latency (one wave per
-// row, 6 waves per compute unit) rather than by the memory pattern, and
-// measured no faster with pieces.
+// minimises max(L + FILL_ROWS, k (T + FILL_ROWS)) (4096 x 4096 in FP32: 35
+// strips of 120 columns, 7 pieces of 567 rows and 11 units taking 3 or 4 tails of 127 rows, against
+// 7 pieces of 586 rows and 11 idle units; FP64, 74 strips of 56 columns:
+// 3 pieces of 1232 rows and 34 units taking 2 or 3 tails of 400 rows).  The
+// launch takes the cheaper form.  A persistent grid that splits the
+// strip-major sequence of (strip, row) evenly over the compute units
+// balances the rows exactly but loses the row alignment of neighbouring
+// strips and their shared halo lines in L2 (18 % slower at 4096 x 4096 in
+// FP32, 1 % in FP64, whose step is bound more by latency: one wave per row,
+// 6 waves per compute unit); it serves grids too short for pieces of 32
+// rows.
 constexpr int FILL_ROWS = 12;
 
 template <typename S>
@@ -102,7 +101,7 @@ Launch fused_launch(const KParams& K) {
     constexpr int TX = StripKernel<S>::TX;
     const int nstrips = (K.nx + TX - 1) / TX;
     const int pmax = K.ny / 32;   // rows per piece stay >= 32
-    if (sizeof(S) == 4 && pmax >= 1) {
+    if (pmax >= 1) {
         // the search runs on every launch of a handle: remember the last grid
         thread_local int last_nx = -1, last_ny = -1, last_cus = -1;
         thread_local Launch last{1, 1, 0};
