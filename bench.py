@@ -313,6 +313,8 @@ def main():
                      "kernel": KERNEL_NAME, "alg_bytes_per_launch": alg_bytes,
                      "kernel_digest": digest},
         "wall_s_timed": wall,
+        "device": {"name": torch.cuda.get_device_properties(0).name,
+                   "compute_units": torch.cuda.get_device_properties(0).multi_processor_count},
     })
     del fa, fb
     s.close()
