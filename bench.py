@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-paper-runs", action="store_true",
                     help="skip the Sod tube and Taylor-Green runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the mixed-against-FP64 error runs at full run lengths")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="grid side of the oracle sample")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -104,12 +106,39 @@ def record_traffic(fetch_csv, write_csv, workload):
     print(json.dumps(rec))
 
 
-def time_steps(solver, f_a, f_b, steps, warmup):
-    """Average time of one step over `steps` steps, measured with HIP events
-    on the stream the library launches on (torch's current stream)."""
+# Least wall time spent stepping before a timed region, whatever --warmup
+# asks for: a GPU that has been idle or busy with other work runs its first
+# few milliseconds of a new load below its steady clock (the first form timed
+# after a short warm-up lost up to 16 %), so the timed steps start only after
+# the step has run this long.
+WARM_FLOOR_S = 1.0
+
+
+def warm_up(solver, f_a, f_b, warmup, floor_s=WARM_FLOOR_S):
+    """`warmup` untimed steps, then more in growing batches until `floor_s`
+    seconds of stepping have passed.  Returns the number of steps run."""
     import torch
+    done = 0
+    t0 = time.perf_counter()
     if warmup > 0:
         solver.step(f_a, f_b, nsteps=warmup)
+        done += warmup
+    torch.cuda.synchronize()
+    batch = 8
+    while time.perf_counter() - t0 < floor_s:
+        solver.step(f_a, f_b, nsteps=batch)
+        torch.cuda.synchronize()
+        done += batch
+        batch = min(2 * batch, 4096)
+    return done
+
+
+def time_steps(solver, f_a, f_b, steps, warmup):
+    """Average time of one step over `steps` steps, measured with HIP events
+    on the stream the library launches on (torch's current stream), after
+    warm_up."""
+    import torch
+    warm_up(solver, f_a, f_b, warmup)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -123,9 +152,18 @@ def time_steps(solver, f_a, f_b, steps, warmup):
     return e0.elapsed_time(e1) / 1e3 / steps, wall
 
 
-def cpu_baseline(run_full, side, steps):
-    """The oracle, as it stands, on a side x side sample of the headline setup."""
-    import torch
+def host_cpus():
+    """CPUs this process may run on (its affinity set) and the machine's count."""
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count()
+    return allowed, os.cpu_count()
+
+
+def oracle_rate(run_full, side, steps):
+    """Updates/s of the oracle, as it stands, on a side x side sample of the
+    headline setup (one warm-up step first), and the seconds it took."""
     import workloads as W
     from oracle import cdbm as C
     run = W.headline_sample(side, seed=run_full_seed(run_full))
@@ -135,12 +173,30 @@ def cpu_baseline(run_full, side, steps):
     t0 = time.perf_counter()
     f = C.run(f, p, steps)
     el = time.perf_counter() - t0
-    ups = 16 * run.cells * steps / el
-    return {"value": ups, "unit": "cell-velocity updates/s", "cores": torch.get_num_threads(),
+    return 16 * run.cells * steps / el, el
+
+
+def cpu_baseline(run_full, side, steps, side_1t=256, steps_1t=4):
+    """The oracle on the host: all threads torch uses on a side x side
+    sample, then one thread on a smaller one."""
+    import torch
+    threads = torch.get_num_threads()
+    ups, el = oracle_rate(run_full, side, steps)
+    torch.set_num_threads(1)
+    try:
+        ups1, el1 = oracle_rate(run_full, side_1t, steps_1t)
+    finally:
+        torch.set_num_threads(threads)
+    allowed, total = host_cpus()
+    return {"value": ups, "unit": "cell-velocity updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{side}x{side} cells of the headline setup (same dx, dt, tau, gamma, "
                       f"velocity set), {steps} FP64 steps after one warm-up step, "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s on {threads} threads",
+            "host_cpus": allowed, "host_cpus_total": total,
+            "value_1thread": ups1,
+            "sample_1thread": f"{side_1t}x{side_1t} cells of the same setup, {steps_1t} FP64 "
+                              f"steps after one warm-up step, {el1:.1f} s on 1 thread"}
 
 
 def copy_bandwidth(torch, nbytes=COPY_BYTES, reps=20):
@@ -183,6 +239,68 @@ def batched_ensemble(steps, warmup):
     del fa, fb
     b.close()
     return res
+
+
+def field_errors(got, want):
+    """Per-field relative L2 errors of (rho, u_x, u_y, T) (device tensors):
+    rho and T against their RMS, the velocities against max |u| (the scale of
+    the relative L2 error of Eq. (25))."""
+    import torch
+    u_scale = float(torch.sqrt(want[1] ** 2 + want[2] ** 2).max())
+    out = {}
+    for n, g, w in zip(("rho", "ux", "uy", "T"), got, want):
+        num = float(torch.sqrt(((g - w) ** 2).mean()))
+        den = u_scale if n in ("ux", "uy") else float(torch.sqrt((w ** 2).mean()))
+        out[n] = num / den
+    return out
+
+
+def headline_accuracy(run):
+    """The headline workload run for its full length in both forms; per-field
+    error of the mixed form against the FP64 one."""
+    from paper_2502_16818_amd import FP64, MIXED, Solver
+    fields = {}
+    for prec in (MIXED, FP64):
+        s = Solver.from_run(run, prec)
+        f = s.init(run.rho, run.ux, run.uy, run.T)
+        g = s.step(f, nsteps=run.steps)
+        del f
+        fields[prec] = [a.clone() for a in s.moments(g)]
+        del g
+        s.close()
+    res = field_errors(fields[MIXED], fields[FP64])
+    res["steps"] = run.steps
+    return res
+
+
+def batched_accuracy(steps=1000):
+    """The 96-grid ensemble for its full 1000 steps in both forms; the worst
+    per-field error of the mixed form against the FP64 one over the grids."""
+    import workloads as W
+    from paper_2502_16818_amd import FP64, MIXED, Batch, Solver, make_params
+    runs = W.batched_ensemble()
+    fields = {}
+    for prec in (MIXED, FP64):
+        ps = [make_params(r.nx, r.ny, r.dx, r.dy, r.dt, r.tau, r.gamma, r.v, r.eta, r.bc_x,
+                          r.bc_y, prec) for r in runs]
+        b = Batch(ps)
+        fa = b.init([(r.rho, r.ux, r.uy, r.T) for r in runs])
+        fb = b.step(fa, nsteps=steps)
+        del fa
+        per = []
+        for k, p in enumerate(ps):
+            s = Solver(p)
+            per.append([a.clone() for a in s.moments(b.view(fb, k))])
+            s.close()
+        fields[prec] = per
+        del fb
+        b.close()
+    worst = {}
+    for k in range(len(runs)):
+        e = field_errors(fields[MIXED][k], fields[FP64][k])
+        for n, v in e.items():
+            worst[n] = max(worst.get(n, 0.0), v)
+    return {"worst_over_grids": worst, "grids": len(runs), "steps": steps}
 
 
 # Exact solution of the Sod problem of the tube run (gamma = 1.4, left
@@ -343,8 +461,27 @@ def main():
         out["paper_runs"] = tube_and_vortex_runs()
 
     if not args.no_adjoint:
+        from paper_2502_16818_amd import FP64 as F64
         from paper_2502_16818_amd.rollout import adjoint_forward_ratio
-        out["adjoint"] = adjoint_forward_ratio()
+        adj = adjoint_forward_ratio(keep_grads=not args.no_accuracy)
+        if not args.no_accuracy:
+            ref = adjoint_forward_ratio(precision=F64, keep_grads=True)
+            names = ("rho0", "ux0", "uy0", "T0", "tau")
+            adj["grad_mixed_vs_fp64_rel_l2"] = {
+                n: float((g - r).norm() / r.norm()) for n, g, r in zip(names, adj.pop("grads"),
+                                                                      ref.pop("grads"))}
+            adj["fp64_ratio"] = ref["ratio"]
+        out["adjoint"] = adj
+
+    if not args.no_accuracy:
+        out["accuracy"] = {
+            "what": "relative L2 of the mixed form against the FP64 form of this library at the "
+                    "workloads' full run lengths (rho and T against their RMS, u against max|u|); "
+                    "the FP64 form itself matches the CPU oracle to 1e-12",
+            "headline": headline_accuracy(run),
+        }
+        if not args.no_batch:
+            out["accuracy"]["batched"] = batched_accuracy()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(run, args.cpu_sample, args.cpu_steps)

@@ -63,7 +63,9 @@ enum { CDBM_STEP_AUTO = 0, CDBM_STEP_FUSED = 1, CDBM_STEP_SPLIT = 2 };
  *               time of Eq. (1) (> 0); dt/tau <= 2 is required (the stable
  *               interval of the two-stage scheme for pure relaxation).
  *   gamma       specific-heat ratio, 1 < gamma <= 2; the extra degrees of
- *               freedom are I = 2/(gamma-1) - 2 (gamma = (D+I+2)/(D+I), D = 2).
+ *               freedom are I = 2/(gamma-1) - 2 (gamma = (D+I+2)/(D+I), D = 2,
+ *               the relation stated under Eq. (5)).  Read only when
+ *               dof_given = 0.
  *   v[4]        (v_a, v_b, v_c, v_d) of Eq. (2), each > 0.  Diagonal groups
  *               have components +-v (speed sqrt(2) v).
  *   eta[4]      (eta_a, eta_b, eta_c, eta_d) of Eq. (3), each >= 0.
@@ -81,7 +83,11 @@ enum { CDBM_STEP_AUTO = 0, CDBM_STEP_FUSED = 1, CDBM_STEP_SPLIT = 2 };
  *               grids, where the fused launch has too few strips to fill the
  *               chip).  CDBM_STEP_AUTO: split up to 2^19 cells (724 x 724)
  *               in the mixed form and 2^18 (512 x 512) in FP64, fused
- *               above.  Ignored by the batched form (always fused). */
+ *               above.  Ignored by the batched form (always fused).
+ *   dof_given   0: the gas is given by gamma.  1: it is given by the extra
+ *               degrees of freedom `extra_dof` = I >= 0 of Eq. (5) (finite),
+ *               and gamma is ignored.  A zero-initialised struct selects
+ *               gamma. */
 typedef struct cdbm_params {
     int32_t nx, ny;
     double dx, dy, dt, tau;
@@ -91,6 +97,8 @@ typedef struct cdbm_params {
     int32_t bc_x, bc_y;
     int32_t precision;
     int32_t step_form;
+    int32_t dof_given;
+    double extra_dof;
 } cdbm_params;
 
 typedef struct cdbm_handle cdbm_handle;
@@ -103,7 +111,15 @@ const char* cdbm_last_error(void);
  * (rows of Eq. (6)), split it into its four parity blocks and invert them in
  * extended precision on the host; allocate the handle's scratch (one f-sized
  * ping-pong buffer and reduction partials) on the current device.
- * Synchronous.  Errors: EINVAL, ESINGULAR, ENOMEM, EHIP. */
+ * Synchronous.  Errors: EINVAL, ESINGULAR, ENOMEM, EHIP.
+ *
+ * Setting up a run is two calls: cdbm_create (parameters, constants and
+ * allocations; synchronous, no fields) and cdbm_init (f = f^eq of the
+ * initial fields into a caller buffer; asynchronous after its field check).
+ * An initialiser that takes the parameters and the fields and returns a
+ * handle is exactly cdbm_create followed by cdbm_init; keeping them apart
+ * lets one handle initialise many states (ensembles, the target runs of a
+ * gradient problem) without rebuilding the constants. */
 int cdbm_create(const cdbm_params* p, cdbm_handle** out);
 
 /* Release everything the handle owns.  NULL is accepted.  Synchronizes the

@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("gamma", ctypes.c_double),
         ("v", ctypes.c_double * 4), ("eta", ctypes.c_double * 4),
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("precision", ctypes.c_int32),
-        ("step_form", ctypes.c_int32),
+        ("step_form", ctypes.c_int32), ("dof_given", ctypes.c_int32),
+        ("extra_dof", ctypes.c_double),
     ]
 
 
@@ -120,15 +121,15 @@ def _ptr(t: Optional[torch.Tensor], dtype: Optional[torch.dtype] = None,
     return t.data_ptr()
 
 
-def gamma_to_extra_dof(gamma: float) -> float:
-    return 2.0 / (gamma - 1.0) - 2.0
-
-
 def make_params(nx, ny, dx, dy, dt, tau, gamma, v, eta, bc_x=PERIODIC, bc_y=PERIODIC,
-                precision=FP64, step_form=0) -> Params:
+                precision=FP64, step_form=0, extra_dof=None) -> Params:
+    """cdbm_params; with extra_dof given, the gas is set by I and gamma is ignored."""
     p = Params()
+    if extra_dof is not None:
+        p.dof_given, p.extra_dof = 1, float(extra_dof)
     p.nx, p.ny = int(nx), int(ny)
-    p.dx, p.dy, p.dt, p.tau, p.gamma = float(dx), float(dy), float(dt), float(tau), float(gamma)
+    p.dx, p.dy, p.dt, p.tau = float(dx), float(dy), float(dt), float(tau)
+    p.gamma = 0.0 if gamma is None else float(gamma)
     for k in range(4):
         p.v[k] = float(v[k])
         p.eta[k] = float(eta[k])

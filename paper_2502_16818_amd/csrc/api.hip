@@ -69,17 +69,78 @@ int check_fields_range(int* flag, const double* rho, const double* ux, const dou
     return CDBM_OK;
 }
 
-void StepGraph::drop() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    exec = nullptr;
-    out = nullptr;
+void StepGraph::drop(Entry& en) {
+    if (en.exec) {
+        if (en.launched && en.done) (void)hipEventSynchronize(en.done);
+        (void)hipGraphExecDestroy(en.exec);
+    }
+    en.exec = nullptr;
+    en.out = nullptr;
+    en.launched = false;
 }
 
 void StepGraph::release() {
-    drop();
+    for (Entry& en : slot) {
+        drop(en);
+        if (en.done) (void)hipEventDestroy(en.done);
+        en.done = nullptr;
+    }
     if (cap) (void)hipStreamDestroy(cap);
     cap = nullptr;
 }
+
+namespace {
+
+// The graph entry that replays GRAPH_STEPS steps into `fout`, captured on
+// first use.
+int graph_for(StepFn fn, const void* ctx, void* fout, void* scratch, StepGraph& graph,
+              StepGraph::Entry** out) {
+    for (StepGraph::Entry& en : graph.slot)
+        if (en.exec && en.out == fout) {
+            *out = &en;
+            return CDBM_OK;
+        }
+    StepGraph::Entry& en = graph.slot[graph.next];
+    graph.next ^= 1;
+    graph.drop(en);
+    hipError_t e;
+    if (!graph.cap) {
+        e = hipStreamCreateWithFlags(&graph.cap, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            graph.cap = nullptr;
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        }
+    }
+    if (!en.done) {
+        e = hipEventCreateWithFlags(&en.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            en.done = nullptr;
+            return hip_fail(e, "hipEventCreateWithFlags");
+        }
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(graph.cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = hipSuccess;
+    for (int s = 0; s < GRAPH_STEPS && le == hipSuccess; ++s)
+        le = (s % 2 == 0) ? fn(ctx, fout, scratch, graph.cap) : fn(ctx, scratch, fout, graph.cap);
+    e = hipStreamEndCapture(graph.cap, &g);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(le != hipSuccess ? le : e, "step graph capture");
+    }
+    e = hipGraphInstantiate(&en.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        en.exec = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    en.out = fout;
+    *out = &en;
+    return CDBM_OK;
+}
+
+}  // namespace
 
 int run_steps(StepFn fn, const void* ctx, const void* fin, void* fout, void* scratch, int nsteps,
               hipStream_t st, StepGraph& graph) {
@@ -100,39 +161,17 @@ int run_steps(StepFn fn, const void* ctx, const void* fin, void* fout, void* scr
     const bool can_graph =
         st == nullptr || (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone);
     if (can_graph && remaining >= GRAPH_STEPS) {
-        if (!graph.exec || graph.out != fout) {
-            graph.drop();
-            if (!graph.cap) {
-                e = hipStreamCreateWithFlags(&graph.cap, hipStreamNonBlocking);
-                if (e != hipSuccess) {
-                    graph.cap = nullptr;
-                    return hip_fail(e, "hipStreamCreateWithFlags");
-                }
-            }
-            hipGraph_t g = nullptr;
-            e = hipStreamBeginCapture(graph.cap, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-            hipError_t le = hipSuccess;
-            for (int s = 0; s < GRAPH_STEPS && le == hipSuccess; ++s)
-                le = (s % 2 == 0) ? fn(ctx, fout, scratch, graph.cap) : fn(ctx, scratch, fout, graph.cap);
-            e = hipStreamEndCapture(graph.cap, &g);
-            if (le != hipSuccess || e != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                return hip_fail(le != hipSuccess ? le : e, "step graph capture");
-            }
-            e = hipGraphInstantiate(&graph.exec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) {
-                graph.exec = nullptr;
-                return hip_fail(e, "hipGraphInstantiate");
-            }
-            graph.out = fout;
-        }
+        StepGraph::Entry* en = nullptr;
+        int rc = graph_for(fn, ctx, fout, scratch, graph, &en);
+        if (rc != CDBM_OK) return rc;
         while (remaining >= GRAPH_STEPS) {
-            e = hipGraphLaunch(graph.exec, st);
+            e = hipGraphLaunch(en->exec, st);
             if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+            en->launched = true;
             remaining -= GRAPH_STEPS;
         }
+        e = hipEventRecord(en->done, st);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
     while (remaining > 0) {
         e = fn(ctx, fout, scratch, st);

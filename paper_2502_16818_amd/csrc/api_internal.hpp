@@ -20,16 +20,26 @@ constexpr int REDUCE_BLOCKS = 1024;
 // A step launcher: advance one time step from `fin` to `fout` on `st`.
 using StepFn = hipError_t (*)(const void* ctx, const void* fin, void* fout, hipStream_t st);
 
-// Captured graph of an even number of steps ping-ponging out -> scratch -> out.
-// The steps are captured on a stream of the handle's own (`cap`, created on
-// first use), so that the graph also serves callers on the null stream; the
-// graph is then launched on the caller's stream.
+// Captured graphs of an even number of steps ping-ponging out -> scratch ->
+// out, one per output buffer for the last two output buffers used (a caller
+// that alternates two buffers, as a checkpointed rollout does, replays both
+// without re-capturing).  The steps are captured on a stream of the
+// handle's own (`cap`, created on first use), so that the graphs also serve
+// callers on the null stream; a graph is then launched on the caller's
+// stream, and an event recorded after its last launch lets the graph be
+// destroyed only once that launch has finished.
 struct StepGraph {
-    hipGraphExec_t exec = nullptr;
-    void* out = nullptr;
+    struct Entry {
+        hipGraphExec_t exec = nullptr;
+        void* out = nullptr;
+        hipEvent_t done = nullptr;   // recorded after the entry's last launch
+        bool launched = false;
+    };
+    Entry slot[2];
+    int next = 0;                    // the entry replaced next
     hipStream_t cap = nullptr;
-    void drop();      // the instantiated graph
-    void release();   // the graph and the capture stream
+    void drop(Entry& e);   // waits for the entry's last launch, then frees its graph
+    void release();        // every graph, event and the capture stream
 };
 
 

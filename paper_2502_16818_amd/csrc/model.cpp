@@ -103,8 +103,16 @@ int build_params(const cdbm_params& p, KParams& k, std::string& err) {
         err = buf;
         return CDBM_EINVAL;
     }
-    if (!(std::isfinite(p.gamma) && p.gamma > 1.0 && p.gamma <= 2.0)) {
+    if (p.dof_given != 0 && p.dof_given != 1) {
+        err = "dof_given must be 0 (gamma given) or 1 (extra_dof given)";
+        return CDBM_EINVAL;
+    }
+    if (p.dof_given == 0 && !(std::isfinite(p.gamma) && p.gamma > 1.0 && p.gamma <= 2.0)) {
         err = "gamma must lie in (1, 2] (I = 2/(gamma-1) - 2 >= 0)";
+        return CDBM_EINVAL;
+    }
+    if (p.dof_given == 1 && !(std::isfinite(p.extra_dof) && p.extra_dof >= 0.0)) {
+        err = "extra_dof (I) must be finite and >= 0";
         return CDBM_EINVAL;
     }
     for (int g = 0; g < 4; ++g) {
@@ -223,7 +231,7 @@ int build_params(const cdbm_params& p, KParams& k, std::string& err) {
         k.cxhf[i] = (float)k.cxh[i];
         k.cyhf[i] = (float)k.cyh[i];
     }
-    k.a = 2.0 + extra_dof(p.gamma);
+    k.a = 2.0 + (p.dof_given ? p.extra_dof : extra_dof(p.gamma));
     k.inv_a = 1.0 / k.a;
     k.z = p.dt / p.tau;
     for (int h = 0; h < 2; ++h)

@@ -99,10 +99,12 @@ def rollout(solver: Solver, rho0, ux0, uy0, T0, tau, nsteps: int, every: int = 1
 
 
 def adjoint_forward_ratio(n: int = 256, steps: int = 2000, every: int = 100,
-                          precision: int = MIXED, seed: int = 0) -> dict:
+                          precision: int = MIXED, seed: int = 0, keep_grads: bool = False) -> dict:
     """Wall-time ratio of the backward to the forward pass of the gradient
     workload: n x n periodic grid, smooth random fields, L2 mismatch of the
-    final density against a target run from perturbed fields with 1.1 tau."""
+    final density against a target run from perturbed fields with 1.1 tau.
+    With keep_grads, the result also holds the gradients ("grads": the four
+    field gradients and dL/dtau, on the device)."""
     import workloads as W
 
     base, tgt = W.adjoint_problem(n=n, seed=seed, steps=steps)
@@ -133,9 +135,11 @@ def adjoint_forward_ratio(n: int = 256, steps: int = 2000, every: int = 100,
         "forward_ms_per_step": (t1 - t0) * 1e3 / steps,
         "backward_ms_per_step": (t2 - t1) * 1e3 / steps,
         "ratio": (t2 - t1) / (t1 - t0),
-        "loss": float(loss),
+        "loss": float(loss.detach()),
         "grad_tau": float(tau.grad),
         "grad_norms": [float(f.grad.norm()) for f in fields],
     }
+    if keep_grads:
+        out["grads"] = [f.grad.detach().clone() for f in fields] + [tau.grad.detach().clone()]
     s.close()
     return out

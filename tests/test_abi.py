@@ -64,11 +64,20 @@ def _params(**kw):
     return make_params(**base)
 
 
+def test_create_rejects_a_bad_gas_selector(lib):
+    p = _params()
+    p.dof_given = 2
+    h = ctypes.c_void_p()
+    assert lib.cdbm_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    assert not h.value and b"dof_given" in lib.cdbm_last_error()
+
+
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(ny=-3), dict(nx=70000), dict(dx=0.0), dict(tau=-1.0),
     dict(dt=3e-4, tau=1e-4), dict(gamma=1.0), dict(gamma=2.5), dict(v=(1.4, 0.0, 1.1, 1.0)),
     dict(eta=(3.0, -1.0, 0.0, 0.0)), dict(bc_x=7), dict(precision=5), dict(step_form=3),
-    dict(step_form=-1),
+    dict(step_form=-1), dict(gamma=None, extra_dof=-1.0), dict(gamma=1.4, extra_dof=float("nan")),
+    dict(gamma=None, extra_dof=float("inf")),
 ])
 def test_create_rejects_invalid_parameters(lib, bad):
     p = _params(**bad)
