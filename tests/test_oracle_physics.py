@@ -103,3 +103,56 @@ def test_taylor_green_convergence(golden_dir):
     slope = np.polyfit(np.log([2 * tg["L"] / n for n in ns]), np.log(errs), 1)[0]
     assert 1.5 < slope < 2.1, (slope, errs)
     assert errs[-1] < 0.05
+
+
+def _fan_cases():
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "riemann_textbook.json")))
+    cases = [(R.State(*t["L"]), R.State(*t["R"]), tab["gamma"]) for t in tab["tests"][:4]]
+    lax = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "paper_printed.json")))["lax_paper"]
+    L, Rt = lax["left"], lax["right"]
+    for g in (1.2, 1.4, 5.0 / 3.0):
+        cases.append((R.State(L[0], L[1], L[0] * L[3]), R.State(Rt[0], Rt[1], Rt[0] * Rt[3]), g))
+    return cases
+
+
+@pytest.mark.parametrize("case", range(7))
+def test_rarefaction_fans_keep_their_riemann_invariants(case):
+    """Inside a rarefaction fan of the sampled exact solution the entropy
+    p / rho^gamma and the Riemann invariant u +- 2c / (gamma - 1) of the
+    family that is not crossed keep the values of the state the fan opens
+    from; the fan's head moves at u_K -+ c_K and its tail at u* -+ c*_K, with
+    the undisturbed and star states just outside (Toro tests 1-4 and the Sec.
+    3.2 Lax states at three gammas)."""
+    L, Rs, g = _fan_cases()[case]
+    st = R.star_state(L, Rs, g)
+    fans = 0
+    for side, K in ((-1, L), (1, Rs)):
+        if st.p > K.p:
+            continue                      # a shock on this side
+        fans += 1
+        cK = math.sqrt(g * K.p / K.rho)
+        rho_s = st.rho_L if side < 0 else st.rho_R
+        cs = math.sqrt(g * st.p / rho_s)
+        head, tail = K.u + side * cK, st.u + side * cs
+        lo, hi = min(head, tail), max(head, tail)
+        xi = np.linspace(lo, hi, 41)[1:-1]
+        rho, u, p = R.sample(L, Rs, g, xi)
+        c = np.sqrt(g * p / rho)
+        inv = u - side * 2.0 * c / (g - 1.0)
+        want = K.u - side * 2.0 * cK / (g - 1.0)
+        assert np.abs(inv - want).max() <= 1e-10 * (abs(want) + cK)
+        ent = p / rho ** g
+        assert np.abs(ent / (K.p / K.rho ** g) - 1.0).max() <= 1e-10
+        # the fan is centred: the characteristic speed u -+ c equals x / t
+        assert np.abs(u + side * c - xi).max() <= 1e-10 * (abs(K.u) + cK)
+        eps = 1e-9 * (hi - lo)
+        outside = head + side * eps
+        r0, u0, p0 = R.sample(L, Rs, g, np.array([outside]))
+        assert (r0[0], u0[0], p0[0]) == (K.rho, K.u, K.p)
+        r1, u1, p1 = R.sample(L, Rs, g, np.array([tail + side * eps]))
+        assert abs(p1[0] - st.p) <= 1e-6 * st.p and abs(r1[0] - rho_s) <= 1e-6 * rho_s
+        r2, u2, p2 = R.sample(L, Rs, g, np.array([tail - side * eps]))
+        assert (r2[0], u2[0], p2[0]) == (rho_s, st.u, st.p)
+    assert fans >= 1
