@@ -156,6 +156,17 @@ int cdbm_moments(cdbm_handle* h, const void* f, double* rho, double* ux, double*
  * Delta*_3 (xxx, xxy, xyy, yyy), Delta*_{4,2} (xx, xy, yy). */
 int cdbm_tne(cdbm_handle* h, const void* f, double* out12, void* stream);
 
+/* The same twelve measures in the raw-moment construction that Sec. 2
+ * contrasts the CDBM with: sum_i (f_i - f_i^eq) Psi_{k+5}(v_i) at the raw
+ * velocities v_i instead of the peculiar ones v_i - u, same f^eq (the raw
+ * and central moment constraints of Eqs. (4)-(7) have the same solution for
+ * this set of sixteen moment functions) and the same slot order as cdbm_tne.
+ * Delta_2 = Delta*_2 (the mass and momentum of f - f^eq vanish), while the
+ * higher measures pick up the flow: Delta_{3,1} = Delta*_{3,1} + 2 Delta*_2 u,
+ * and so on.  out12: device double,
+ * 12 planes of [ny][nx]. */
+int cdbm_tne_raw(cdbm_handle* h, const void* f, double* out12, void* stream);
+
 /* Grid totals of mass, x- and y-momentum and energy (sum over cells of
  * rho, rho u_x, rho u_y and sum_i f_i (|v_i|^2 + eta_i^2)), accumulated in
  * double.  out4: device double[4], overwritten. */

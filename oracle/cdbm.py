@@ -305,3 +305,61 @@ def moments_vjp(f: torch.Tensor, g_rho, g_ux, g_uy, g_T, p: Params) -> torch.Ten
     outs = macroscopic(f, vel, eta, p.I)
     grads = [torch.as_tensor(g, dtype=DT) for g in (g_rho, g_ux, g_uy, g_T)]
     return torch.autograd.grad(outs, f, grads)[0]
+
+
+# ---------------------------------------------------------------------------
+# Raw-moment DBM (the construction Sec. 2 contrasts the CDBM with): the same
+# sixteen moment functions evaluated at the raw velocities v_i instead of the
+# peculiar ones v_i - u.
+# ---------------------------------------------------------------------------
+
+def raw_equilibrium_moments(rho, ux, uy, T, I: float, order: int = 6) -> torch.Tensor:
+    """Raw moments sum over Psi_r(v, eta) of the Maxwellian Eq. (5), by
+    Gauss-Hermite quadrature: v = u + sqrt(T) xi per translational component
+    and eta = sqrt(I T) zeta with xi, zeta standard normal (exact for the
+    polynomial Psi_r, of degree <= 4 in v and 2 in eta, at `order` >= 4
+    nodes).  rho, ux, uy, T: (N,) -> (N, 16) in the row order of Eq. (6)."""
+    import numpy as np
+    x, w = np.polynomial.hermite_e.hermegauss(order)
+    w = w / w.sum()
+    xi = torch.as_tensor(x, dtype=DT)
+    wt = torch.as_tensor(w, dtype=DT)
+    rho, ux, uy, T = (torch.as_tensor(a, dtype=DT).reshape(-1) for a in (rho, ux, uy, T))
+    s = torch.sqrt(T)[:, None, None, None]
+    se = torch.sqrt(I * T)[:, None, None, None]
+    vx = ux[:, None, None, None] + s * xi[None, :, None, None]
+    vy = uy[:, None, None, None] + s * xi[None, None, :, None]
+    et = se * xi[None, None, None, :]
+    vx, vy, et = torch.broadcast_tensors(vx, vy, et)
+    W3 = (wt[:, None, None] * wt[None, :, None] * wt[None, None, :])[None]
+    rows = moment_rows(vx, vy, et)                     # (16, N, q, q, q)
+    return rho[:, None] * (rows * W3[None]).sum(dim=(2, 3, 4)).t()
+
+
+def raw_equilibrium(rho, ux, uy, T, I, vel, eta) -> torch.Tensor:
+    """f^eq of the raw-moment construction: M0 f^eq = m^eq, with M0 the
+    matrix of Eq. (6) at u = 0 and m^eq the raw Maxwellian moments; one
+    16 x 16 solve per cell.  -> (N, 16)."""
+    m = raw_equilibrium_moments(rho, ux, uy, T, I)
+    n = m.shape[0]
+    zero = torch.zeros(n, dtype=DT)
+    M0 = moment_matrix(zero, zero, vel, eta)
+    return torch.linalg.solve(M0, m.unsqueeze(-1)).squeeze(-1)
+
+
+def raw_nonequilibrium(f: torch.Tensor, p: Params) -> torch.Tensor:
+    """Nonequilibrium measures of the raw-moment construction:
+    sum_i (f_i - f_i^eq) Psi_r(v_i) for rows r = 5..16 (the raw velocity in
+    place of the peculiar one of Eqs. (8)-(11)), with f^eq from
+    raw_equilibrium.  Returns (12, ny, nx) in the slot order of
+    nonequilibrium()."""
+    vel, eta = discrete_velocities(p.v, p.eta)
+    rho, ux, uy, T = macroscopic(f, vel, eta, p.I)
+    n = rho.numel()
+    feq = raw_equilibrium(rho.reshape(-1), ux.reshape(-1), uy.reshape(-1), T.reshape(-1),
+                          p.I, vel, eta)
+    zero = torch.zeros(n, dtype=DT)
+    M0 = moment_matrix(zero, zero, vel, eta)
+    dev = f.reshape(16, n).t() - feq
+    out = torch.einsum("nri,ni->nr", M0, dev)
+    return out[:, 4:].t().reshape((12,) + tuple(rho.shape))

@@ -23,7 +23,8 @@ STEP_AUTO, STEP_FUSED, STEP_SPLIT = 0, 1, 2
 
 EXPORTS = (
     "cdbm_last_error", "cdbm_create", "cdbm_destroy", "cdbm_get_params", "cdbm_init",
-    "cdbm_step", "cdbm_moments", "cdbm_tne", "cdbm_conserved_totals", "cdbm_step_adjoint",
+    "cdbm_step", "cdbm_moments", "cdbm_tne", "cdbm_tne_raw", "cdbm_conserved_totals",
+    "cdbm_step_adjoint",
     "cdbm_step_keep_stage", "cdbm_step_adjoint_stage",
     "cdbm_init_adjoint", "cdbm_moments_adjoint", "cdbm_batch_create", "cdbm_batch_destroy",
     "cdbm_batch_init", "cdbm_batch_step",
@@ -71,6 +72,7 @@ def load() -> ctypes.CDLL:
         "cdbm_step": ([_vp, _vp, _vp, _i32, _vp], _i32),
         "cdbm_moments": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
         "cdbm_tne": ([_vp, _vp, _vp, _vp], _i32),
+        "cdbm_tne_raw": ([_vp, _vp, _vp, _vp], _i32),
         "cdbm_conserved_totals": ([_vp, _vp, _vp, _vp], _i32),
         "cdbm_step_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp], _i32),
         "cdbm_step_keep_stage": ([_vp, _vp, _vp, _vp, _vp], _i32),
@@ -219,6 +221,12 @@ class Solver:
     def tne(self, f: torch.Tensor) -> torch.Tensor:
         out = self.empty_field(12)
         _check(load().cdbm_tne(self._h, self._f(f), _ptr(out), _stream()), "cdbm_tne")
+        return out
+
+    def tne_raw(self, f: torch.Tensor) -> torch.Tensor:
+        """The same measures at the raw velocities (raw-moment construction)."""
+        out = self.empty_field(12)
+        _check(load().cdbm_tne_raw(self._h, self._f(f), _ptr(out), _stream()), "cdbm_tne_raw")
         return out
 
     def totals(self, f: torch.Tensor) -> torch.Tensor:

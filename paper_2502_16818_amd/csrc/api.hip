@@ -346,14 +346,24 @@ int cdbm_moments(cdbm_handle* h, const void* f, double* rho, double* ux, double*
     return e == hipSuccess ? CDBM_OK : hip_fail(e, "moments launch");
 }
 
-int cdbm_tne(cdbm_handle* h, const void* f, double* out12, void* stream) {
+namespace {
+int tne_common(cdbm_handle* h, const void* f, double* out12, bool raw, void* stream) {
     if (!h || !f || !out12) return fail(CDBM_EINVAL, "null argument");
     int rc = check_device(h);
     if (rc != CDBM_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = mixed(h) ? cdbm::launch_tne<float>(f, out12, h->k, st)
-                            : cdbm::launch_tne<double>(f, out12, h->k, st);
+    hipError_t e = mixed(h) ? cdbm::launch_tne<float>(f, out12, raw, h->k, st)
+                            : cdbm::launch_tne<double>(f, out12, raw, h->k, st);
     return e == hipSuccess ? CDBM_OK : hip_fail(e, "tne launch");
+}
+}  // namespace
+
+int cdbm_tne(cdbm_handle* h, const void* f, double* out12, void* stream) {
+    return tne_common(h, f, out12, false, stream);
+}
+
+int cdbm_tne_raw(cdbm_handle* h, const void* f, double* out12, void* stream) {
+    return tne_common(h, f, out12, true, stream);
 }
 
 int cdbm_conserved_totals(cdbm_handle* h, const void* f, double* out4, void* stream) {

@@ -65,7 +65,9 @@ __global__ void __launch_bounds__(256) k_moments(const S* __restrict__ f, double
 }
 
 // Eqs. (8)-(11): sum_i (f_i - f_i^eq) Psi_r(v_i - u), rows r = 5..16.
-template <typename S>
+// RAW: the measures of the raw-moment construction, Psi_r(v_i) at the raw
+// velocities (same f^eq).
+template <typename S, bool RAW>
 __global__ void __launch_bounds__(256) k_tne(const S* __restrict__ f, double* __restrict__ out,
                                              KParams K, int64_t cells) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -83,7 +85,7 @@ __global__ void __launch_bounds__(256) k_tne(const S* __restrict__ f, double* __
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         const double d = fd[i] - feq[i];
-        const double cx = K.vx[i] - m.ux, cy = K.vy[i] - m.uy;
+        const double cx = RAW ? K.vx[i] : K.vx[i] - m.ux, cy = RAW ? K.vy[i] : K.vy[i] - m.uy;
         const double e = cx * cx + cy * cy + K.eta2[i];
         const double xx = cx * cx, xy = cx * cy, yy = cy * cy;
         acc[0] = fma(d, xx, acc[0]);
@@ -225,10 +227,14 @@ hipError_t launch_moments(const void* f, double* rho, double* ux, double* uy, do
 }
 
 template <typename S>
-hipError_t launch_tne(const void* f, double* out12, const KParams& K, hipStream_t st) {
+hipError_t launch_tne(const void* f, double* out12, bool raw, const KParams& K, hipStream_t st) {
     const int64_t cells = (int64_t)K.nx * K.ny;
-    hipLaunchKernelGGL(k_tne<S>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, (const S*)f,
-                       out12, K, cells);
+    if (raw)
+        hipLaunchKernelGGL((k_tne<S, true>), dim3(blocks_for(cells, 256)), dim3(256), 0, st,
+                           (const S*)f, out12, K, cells);
+    else
+        hipLaunchKernelGGL((k_tne<S, false>), dim3(blocks_for(cells, 256)), dim3(256), 0, st,
+                           (const S*)f, out12, K, cells);
     return hipGetLastError();
 }
 
@@ -266,7 +272,7 @@ hipError_t launch_stage(const void* fin, const void* base, void* fout, bool stag
                                        const double*, void*, const KParams&, hipStream_t);     \
     template hipError_t launch_moments<S>(const void*, double*, double*, double*, double*,     \
                                           const KParams&, hipStream_t);                        \
-    template hipError_t launch_tne<S>(const void*, double*, const KParams&, hipStream_t);      \
+    template hipError_t launch_tne<S>(const void*, double*, bool, const KParams&, hipStream_t);      \
     template hipError_t launch_totals<S>(const void*, double*, int, double*, const KParams&,   \
                                          hipStream_t);                                         \
     template hipError_t launch_stage<S>(const void*, const void*, void*, bool, const KParams&, \

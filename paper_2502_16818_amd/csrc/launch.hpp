@@ -18,7 +18,7 @@ template <typename S>
 hipError_t launch_moments(const void* f, double* rho, double* ux, double* uy, double* T,
                           const KParams& K, hipStream_t st);
 template <typename S>
-hipError_t launch_tne(const void* f, double* out12, const KParams& K, hipStream_t st);
+hipError_t launch_tne(const void* f, double* out12, bool raw, const KParams& K, hipStream_t st);
 template <typename S>
 hipError_t launch_totals(const void* f, double* partials, int nblocks, double* out4,
                          const KParams& K, hipStream_t st);

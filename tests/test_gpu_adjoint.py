@@ -258,13 +258,23 @@ def test_gradient_workload_full_size():
                 f = s.step(s.init(*fields), nsteps=steps)
                 return ((s.moments(f)[0] - rho_t) ** 2).mean().item()
 
-            h = 1e-4   # the step the gradient workload specifies for its central differences
             ds = dirsets[0]
-            fd = (loss_at([a + h * d for a, d in zip(f0, ds)]) -
-                  loss_at([a - h * d for a, d in zip(f0, ds)])) / (2 * h)
+
+            def central(h):
+                return (loss_at([a + h * d for a, d in zip(f0, ds)]) -
+                        loss_at([a - h * d for a, d in zip(f0, ds)])) / (2 * h)
+
+            # h = 1e-4 is the step the gradient workload specifies.  The loss
+            # is only piecewise smooth along d (minmod switches), and a step
+            # that large crosses switches and carries the O(h^2) error of the
+            # difference: measured 0.8 % off, gated at 2 %.  h = 1e-5 stays
+            # within 1e-3.
+            fd4, fd5 = central(1e-4), central(1e-5)
             s.close()
-            print(f"  fp64 adjoint {d64[0]:.6e} vs central difference {fd:.6e}")
-            assert abs(d64[0] - fd) <= 1e-3 * abs(fd)
+            print(f"  fp64 adjoint {d64[0]:.6e} vs central differences {fd4:.6e} (h = 1e-4), "
+                  f"{fd5:.6e} (h = 1e-5)")
+            assert abs(d64[0] - fd4) <= 2e-2 * abs(fd4)
+            assert abs(d64[0] - fd5) <= 1e-3 * abs(fd5)
             for a, b in zip(d32, d64):
                 assert abs(a - b) <= 0.1 * abs(b)
         else:
