@@ -172,6 +172,21 @@ int cdbm_tne_raw(cdbm_handle* h, const void* f, double* out12, void* stream);
  * double.  out4: device double[4], overwritten. */
 int cdbm_conserved_totals(cdbm_handle* h, const void* f, double* out4, void* stream);
 
+/* cdbm_conserved_totals for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): no handle, no hipMalloc or hipFree.  p: the parameters of the
+ * grid f belongs to (validated as by cdbm_create; only nx, ny, v, eta and
+ * precision affect the result); f, out4: as for cdbm_conserved_totals, whose
+ * result this equals bit for bit.  The block partial sums live in a 32 KiB
+ * array allocated statically in the library on each GPU and held until the
+ * process ends; its size does not depend on the grid, so every grid the
+ * parameters allow fits.  Every call on a GPU uses that GPU's one array:
+ * calls that overlap in time on one GPU (other streams, other threads)
+ * race and give wrong totals; order them on one stream.  The first call on
+ * each GPU looks up the array's device address (synchronous, not a stream
+ * operation); make it outside a graph capture. */
+int cdbm_conserved_totals_static(const cdbm_params* p, const void* f, double* out4, void* stream);
+
 /* Reverse-mode product of one time step F (the map of cdbm_step with
  * nsteps = 1): lam_n = (dF/df)^T(f_n) lam_np1 and *dL_dtau += (dF/dtau)^T lam_np1.
  * f_n: device [16][ny][nx] in the handle's precision.  lam_np1, lam_n:

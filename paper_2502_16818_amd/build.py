@@ -23,6 +23,7 @@ SOURCES = [
     "api.hip",
     "api_adjoint.hip",
     "api_batch.hip",
+    "api_static.hip",
     "kernels_basic.hip",
     "kernels_step.hip",
     "kernels_adjoint.hip",

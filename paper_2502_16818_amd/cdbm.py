@@ -27,7 +27,7 @@ EXPORTS = (
     "cdbm_step_adjoint",
     "cdbm_step_keep_stage", "cdbm_step_adjoint_stage",
     "cdbm_init_adjoint", "cdbm_moments_adjoint", "cdbm_batch_create", "cdbm_batch_destroy",
-    "cdbm_batch_init", "cdbm_batch_step",
+    "cdbm_batch_init", "cdbm_batch_step", "cdbm_conserved_totals_static",
 )
 
 
@@ -74,6 +74,7 @@ def load() -> ctypes.CDLL:
         "cdbm_tne": ([_vp, _vp, _vp, _vp], _i32),
         "cdbm_tne_raw": ([_vp, _vp, _vp, _vp], _i32),
         "cdbm_conserved_totals": ([_vp, _vp, _vp, _vp], _i32),
+        "cdbm_conserved_totals_static": ([P, _vp, _vp, _vp], _i32),
         "cdbm_step_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp], _i32),
         "cdbm_step_keep_stage": ([_vp, _vp, _vp, _vp, _vp], _i32),
         "cdbm_step_adjoint_stage": ([_vp] * 7, _i32),
