@@ -220,7 +220,9 @@ def copy_bandwidth(torch, nbytes=COPY_BYTES, reps=20):
 
 def batched_ensemble(steps, warmup):
     """The 96-grid ensemble (sizes 128..1024, own gamma and tau per grid) in
-    the mixed form, one persistent launch per step."""
+    the mixed form, one persistent launch per step: timed with the default
+    launch layout, then with the one the autotuner picks (cache file from
+    CDBM_TUNE_CACHE, if set)."""
     import torch
     import workloads as W
     from paper_2502_16818_amd import MIXED, Batch, make_params
@@ -230,12 +232,19 @@ def batched_ensemble(steps, warmup):
     b = Batch(ps)
     fa = b.init([(r.rho, r.ux, r.uy, r.T) for r in runs])
     fb = b.empty_f()
+    t_default, _ = time_steps(b, fa, fb, steps, warmup)
+    default = b.get_launch()
+    t0 = time.perf_counter()
+    chosen = b.autotune(fa, fb, os.environ.get("CDBM_TUNE_CACHE"))
+    tune_s = time.perf_counter() - t0
     t, _ = time_steps(b, fa, fb, steps, warmup)
     cells = sum(r.cells for r in runs)
     ach = 2 * 4 * 16 * cells / t / 1e9
     res = {"grids": len(runs), "cells": cells, "steps": steps, "ms_per_step": t * 1e3,
            "value": 16 * cells / t, "unit": "cell-velocity updates/s",
-           "roofline_frac": ach / HBM_PEAK_GBS, "achieved_GBs": ach}
+           "roofline_frac": ach / HBM_PEAK_GBS, "achieved_GBs": ach,
+           "launch": chosen, "autotune_s": tune_s,
+           "default_launch": default, "default_ms_per_step": t_default * 1e3}
     del fa, fb
     b.close()
     return res

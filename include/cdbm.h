@@ -256,6 +256,45 @@ int cdbm_batch_init(cdbm_batch* b, const double* rho, const double* ux, const do
  * replayed. */
 int cdbm_batch_step(cdbm_batch* b, const void* f_in, void* f_out, int32_t nsteps, void* stream);
 
+/* How the batched step spreads the grids' strips over its persistent
+ * blocks (one block per compute unit); every layout gives bit-identical
+ * results.
+ *   CDBM_BATCH_CONTIGUOUS: the (grid, strip, row) sequence cut into equal
+ *     contiguous pieces, one per block, each strip weighing its rows plus
+ *     fill_rows (the pipeline fill of a segment; default 14).
+ *   CDBM_BATCH_ROW_PIECES: every grid cut into row pieces of about
+ *     piece_rows rows; the units (grid, piece, strip) are taken in order from
+ *     one counter per XCD, so that the blocks of an XCD work on neighbouring
+ *     strips of the same rows at the same time.
+ * `reserved` must be 0. */
+enum { CDBM_BATCH_CONTIGUOUS = 0, CDBM_BATCH_ROW_PIECES = 1 };
+typedef struct cdbm_batch_launch {
+    int32_t layout;
+    int32_t fill_rows;    /* CONTIGUOUS: 0 .. 1024 */
+    int32_t piece_rows;   /* ROW_PIECES: 16 .. 65536 */
+    int32_t reserved;
+} cdbm_batch_launch;
+
+/* The batch's current launch layout. */
+int cdbm_batch_get_launch(const cdbm_batch* b, cdbm_batch_launch* out);
+
+/* Select a launch layout (synchronous: uploads its tables; drops the
+ * captured step graphs).  Errors: EINVAL for a layout out of range. */
+int cdbm_batch_set_launch(cdbm_batch* b, const cdbm_batch_launch* l);
+
+/* Autotuner of the batched step.  Looks up the batch's key (the device's gfx
+ * architecture, the precision form, and floor(log2) of the batch's cell and
+ * grid counts) in the JSON cache file `cache_path` (NULL: no cache) and
+ * applies the stored layout; otherwise times the candidate layouts (the
+ * contiguous split with fill_rows 0, 14, 28 and row pieces of 128, 192 and
+ * 256 rows; 26 steps each), applies the fastest and adds it to the cache
+ * (written through a temporary file; an unwritable cache is skipped).  f_in:
+ * a state of the batch (read only); f_out and the batch's scratch buffer are
+ * overwritten by the timing steps.  `chosen` (may be NULL) receives the
+ * layout applied.  Synchronous. */
+int cdbm_batch_autotune(cdbm_batch* b, const void* f_in, void* f_out, const char* cache_path,
+                        cdbm_batch_launch* chosen, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,6 +6,6 @@ This package holds the build script, the ctypes binding and the autograd
 wrapper of the hand-written adjoint.
 """
 from .cdbm import (  # noqa: F401
-    EXPORTS, FP64, MIXED, PERIODIC, ZERO_GRADIENT, Batch, CdbmError, Params, Solver, load,
-    make_params,
+    BATCH_CONTIGUOUS, BATCH_ROW_PIECES, EXPORTS, FP64, MIXED, PERIODIC, ZERO_GRADIENT, Batch,
+    CdbmError, Params, Solver, load, make_params,
 )

@@ -28,7 +28,19 @@ EXPORTS = (
     "cdbm_step_keep_stage", "cdbm_step_adjoint_stage",
     "cdbm_init_adjoint", "cdbm_moments_adjoint", "cdbm_batch_create", "cdbm_batch_destroy",
     "cdbm_batch_init", "cdbm_batch_step", "cdbm_conserved_totals_static",
+    "cdbm_batch_get_launch", "cdbm_batch_set_launch", "cdbm_batch_autotune",
 )
+
+
+BATCH_CONTIGUOUS, BATCH_ROW_PIECES = 0, 1
+
+
+class BatchLaunch(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_int32), ("fill_rows", ctypes.c_int32),
+                ("piece_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"layout": self.layout, "fill_rows": self.fill_rows, "piece_rows": self.piece_rows}
 
 
 class CdbmError(RuntimeError):
@@ -84,6 +96,10 @@ def load() -> ctypes.CDLL:
         "cdbm_batch_destroy": ([_vp], _i32),
         "cdbm_batch_init": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
         "cdbm_batch_step": ([_vp, _vp, _vp, _i32, _vp], _i32),
+        "cdbm_batch_get_launch": ([_vp, ctypes.POINTER(BatchLaunch)], _i32),
+        "cdbm_batch_set_launch": ([_vp, ctypes.POINTER(BatchLaunch)], _i32),
+        "cdbm_batch_autotune": ([_vp, _vp, _vp, ctypes.c_char_p, ctypes.POINTER(BatchLaunch), _vp],
+                                _i32),
     }
     for name, (args, res) in sig.items():
         if not hasattr(lib, name):
@@ -330,6 +346,27 @@ class Batch:
                                       _ptr(out, self.dtype, self.total), _stream()),
                "cdbm_batch_init")
         return out
+
+    def get_launch(self) -> dict:
+        out = BatchLaunch()
+        _check(load().cdbm_batch_get_launch(self._b, ctypes.byref(out)), "cdbm_batch_get_launch")
+        return out.as_dict()
+
+    def set_launch(self, layout: int = BATCH_CONTIGUOUS, fill_rows: int = 14,
+                   piece_rows: int = 0) -> None:
+        l = BatchLaunch(int(layout), int(fill_rows), int(piece_rows), 0)
+        _check(load().cdbm_batch_set_launch(self._b, ctypes.byref(l)), "cdbm_batch_set_launch")
+
+    def autotune(self, f_in: torch.Tensor, f_out: torch.Tensor,
+                 cache_path: Optional[str] = None) -> dict:
+        """Pick the launch layout by timing (or from the JSON cache file);
+        f_out is overwritten.  Returns the layout applied."""
+        out = BatchLaunch()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(load().cdbm_batch_autotune(self._b, _ptr(f_in, self.dtype, self.total),
+                                          _ptr(f_out, self.dtype, self.total), path,
+                                          ctypes.byref(out), _stream()), "cdbm_batch_autotune")
+        return out.as_dict()
 
     def step(self, f_in: torch.Tensor, f_out: Optional[torch.Tensor] = None,
              nsteps: int = 1) -> torch.Tensor:

@@ -32,6 +32,14 @@ struct cdbm_batch {
     void* scratch = nullptr;
     int nblocks = 1;
     bool chunked = false;   // every width and offset is a multiple of the 16-byte chunk
+    cdbm_batch_launch launch{CDBM_BATCH_CONTIGUOUS, BATCH_FILL, 0, 0};
+    // row-piece form: unit prefix sums, per-grid (strips, pieces, rows), the
+    // counter ranges and the counters themselves
+    int64_t* d_units = nullptr;
+    int* d_geom = nullptr;
+    int64_t* d_range = nullptr;
+    int* d_counters = nullptr;
+    int nq = 1;
     StepGraph graph;
 };
 
@@ -44,17 +52,268 @@ void release(cdbm_batch* b) {
     if (b->d_work) (void)hipFree(b->d_work);
     if (b->flag) (void)hipFree(b->flag);
     if (b->scratch) (void)hipFree(b->scratch);
+    if (b->d_units) (void)hipFree(b->d_units);
+    if (b->d_geom) (void)hipFree(b->d_geom);
+    if (b->d_range) (void)hipFree(b->d_range);
+    if (b->d_counters) (void)hipFree(b->d_counters);
     delete b;
 }
 
 hipError_t batch_step_once(const void* ctx, const void* fin, void* fout, hipStream_t st) {
     const cdbm_batch* b = (const cdbm_batch*)ctx;
     const int n = (int)b->p.size();
+    if (b->launch.layout == CDBM_BATCH_ROW_PIECES)
+        return b->precision == CDBM_MIXED
+                   ? launch_batch_step_rows<float>(fin, fout, b->d_k, b->d_off, b->d_units,
+                                                   b->d_geom, b->d_range, b->nq, b->d_counters,
+                                                   b->nblocks, b->chunked, st)
+                   : launch_batch_step_rows<double>(fin, fout, b->d_k, b->d_off, b->d_units,
+                                                    b->d_geom, b->d_range, b->nq, b->d_counters,
+                                                    b->nblocks, b->chunked, st);
     return b->precision == CDBM_MIXED
-               ? launch_batch_step<float>(fin, fout, b->d_k, b->d_off, b->d_work, n, b->nblocks,
-                                          b->chunked, st)
-               : launch_batch_step<double>(fin, fout, b->d_k, b->d_off, b->d_work, n, b->nblocks,
-                                           b->chunked, st);
+               ? launch_batch_step<float>(fin, fout, b->d_k, b->d_off, b->d_work, n,
+                                          b->launch.fill_rows, b->nblocks, b->chunked, st)
+               : launch_batch_step<double>(fin, fout, b->d_k, b->d_off, b->d_work, n,
+                                           b->launch.fill_rows, b->nblocks, b->chunked, st);
+}
+
+int check_launch(const cdbm_batch_launch& l) {
+    if (l.layout != CDBM_BATCH_CONTIGUOUS && l.layout != CDBM_BATCH_ROW_PIECES)
+        return fail(CDBM_EINVAL, "layout must be CDBM_BATCH_CONTIGUOUS or CDBM_BATCH_ROW_PIECES");
+    if (l.layout == CDBM_BATCH_CONTIGUOUS && (l.fill_rows < 0 || l.fill_rows > 1024))
+        return fail(CDBM_EINVAL, "fill_rows must lie in [0, 1024]");
+    if (l.layout == CDBM_BATCH_ROW_PIECES && (l.piece_rows < 16 || l.piece_rows > 65536))
+        return fail(CDBM_EINVAL, "piece_rows must lie in [16, 65536]");
+    return CDBM_OK;
+}
+
+// Upload the tables of a launch configuration (synchronous).  Contiguous
+// form: the prefix sums of strips * (ny + fill).  Row-piece form: each grid
+// cut into pieces of about piece_rows rows; the units (grid, piece, strip)
+// split into nq ranges of about equal weight (rows + BATCH_FILL per unit),
+// nq = min(8, blocks): one counter per XCD.
+int apply_launch(cdbm_batch* b, const cdbm_batch_launch& l) {
+    int rc = check_launch(l);
+    if (rc != CDBM_OK) return rc;
+    // the captured graphs hold the old kernel and its arguments
+    b->graph.release();
+    const int n = (int)b->p.size();
+    const int tx = strip_width(b->precision);
+    hipError_t e;
+    if (l.layout == CDBM_BATCH_CONTIGUOUS) {
+        std::vector<int64_t> work(n + 1, 0);
+        for (int g = 0; g < n; ++g) {
+            const int64_t strips = (b->p[g].nx + tx - 1) / tx;
+            work[g + 1] = work[g] + strips * (b->p[g].ny + l.fill_rows);
+        }
+        e = hipMemcpy(b->d_work, work.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy of the batch work table");
+    } else {
+        std::vector<int64_t> units(n + 1, 0);
+        std::vector<int> geom(3 * n);
+        std::vector<double> weight;   // per unit
+        for (int g = 0; g < n; ++g) {
+            const int ny = b->p[g].ny;
+            const int strips = (b->p[g].nx + tx - 1) / tx;
+            int pieces = std::max(1, (ny + l.piece_rows / 2) / l.piece_rows);
+            const int rows = (ny + pieces - 1) / pieces;
+            pieces = (ny + rows - 1) / rows;
+            geom[3 * g] = strips;
+            geom[3 * g + 1] = pieces;
+            geom[3 * g + 2] = rows;
+            units[g + 1] = units[g] + (int64_t)strips * pieces;
+            for (int p = 0; p < pieces; ++p) {
+                const int len = std::min(ny, (p + 1) * rows) - p * rows;
+                for (int s = 0; s < strips; ++s) weight.push_back(len + BATCH_FILL);
+            }
+        }
+        if (units[n] >= (int64_t(1) << 31)) return fail(CDBM_EINVAL, "too many work units");
+        const int nq = std::max(1, std::min(8, b->nblocks));
+        std::vector<int64_t> range(nq + 1, units[n]);
+        double total = 0.0;
+        for (double w : weight) total += w;
+        double acc = 0.0;
+        int k = 1;
+        range[0] = 0;
+        for (int64_t u = 0; u < units[n] && k < nq; ++u) {
+            acc += weight[u];
+            while (k < nq && acc >= total * k / nq) range[k++] = u + 1;
+        }
+        if (!b->d_units) {
+            if (hipMalloc(&b->d_units, sizeof(int64_t) * (n + 1)) != hipSuccess ||
+                hipMalloc(&b->d_geom, sizeof(int) * 3 * n) != hipSuccess ||
+                hipMalloc(&b->d_range, sizeof(int64_t) * 9) != hipSuccess ||
+                hipMalloc(&b->d_counters, sizeof(int) * 9) != hipSuccess)
+                return fail(CDBM_ENOMEM, "device allocation of the row-piece tables failed");
+        }
+        if ((e = hipMemcpy(b->d_units, units.data(), sizeof(int64_t) * (n + 1),
+                           hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(b->d_geom, geom.data(), sizeof(int) * 3 * n, hipMemcpyHostToDevice)) !=
+                hipSuccess ||
+            (e = hipMemcpy(b->d_range, range.data(), sizeof(int64_t) * (nq + 1),
+                           hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemset(b->d_counters, 0, sizeof(int) * 9)) != hipSuccess ||
+            (e = hipDeviceSynchronize()) != hipSuccess)
+            return hip_fail(e, "upload of the row-piece tables");
+        b->nq = nq;
+    }
+    b->launch = l;
+    return CDBM_OK;
+}
+
+// --- autotuning ----------------------------------------------------------
+//
+// The cache is a JSON object with one entry per line, keyed by
+// "<gfx arch>|<precision>|cells2^<k>|grids2^<m>" (k, m: floor of log2 of the
+// batch's cell and grid counts), each value the chosen launch and its time:
+//   "gfx950|mixed|cells2^25|grids2^6": {"layout": 1, "fill_rows": 14, "piece_rows": 192, "ms_per_step": 1.612},
+
+struct TuneEntry {
+    cdbm_batch_launch l;
+    double ms;
+};
+
+int floor_log2(int64_t v) {
+    int k = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++k;
+    }
+    return k;
+}
+
+std::string tune_key(const cdbm_batch* b) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos) arch = arch.substr(0, c);
+    }
+    int64_t cells = 0;
+    for (const cdbm_params& q : b->p) cells += (int64_t)q.nx * q.ny;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s|%s|cells2^%d|grids2^%d", arch.c_str(),
+                  b->precision == CDBM_MIXED ? "mixed" : "fp64", floor_log2(cells),
+                  floor_log2((int64_t)b->p.size()));
+    return buf;
+}
+
+std::vector<std::pair<std::string, TuneEntry>> read_cache(const char* path) {
+    std::vector<std::pair<std::string, TuneEntry>> out;
+    FILE* fh = path ? std::fopen(path, "r") : nullptr;
+    if (!fh) return out;
+    char line[512];
+    while (std::fgets(line, sizeof line, fh)) {
+        const char* q0 = std::strchr(line, '"');
+        const char* q1 = q0 ? std::strchr(q0 + 1, '"') : nullptr;
+        const char* brace = q1 ? std::strchr(q1, '{') : nullptr;
+        if (!brace) continue;
+        TuneEntry e{};
+        if (std::sscanf(brace, "{\"layout\": %d, \"fill_rows\": %d, \"piece_rows\": %d, "
+                               "\"ms_per_step\": %lf",
+                        &e.l.layout, &e.l.fill_rows, &e.l.piece_rows, &e.ms) != 4)
+            continue;
+        out.emplace_back(std::string(q0 + 1, q1), e);
+    }
+    std::fclose(fh);
+    return out;
+}
+
+void write_cache(const char* path, const std::vector<std::pair<std::string, TuneEntry>>& ents) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* fh = std::fopen(tmp.c_str(), "w");
+    if (!fh) return;   // an unwritable cache only costs a re-tune next time
+    std::fprintf(fh, "{\n");
+    for (size_t k = 0; k < ents.size(); ++k) {
+        const TuneEntry& e = ents[k].second;
+        std::fprintf(fh,
+                     "\"%s\": {\"layout\": %d, \"fill_rows\": %d, \"piece_rows\": %d, "
+                     "\"ms_per_step\": %.6f}%s\n",
+                     ents[k].first.c_str(), e.l.layout, e.l.fill_rows, e.l.piece_rows, e.ms,
+                     k + 1 < ents.size() ? "," : "");
+    }
+    std::fprintf(fh, "}\n");
+    std::fclose(fh);
+    std::rename(tmp.c_str(), path);
+}
+
+// Milliseconds per step of the current launch: the fastest of three runs of
+// TUNE_STEPS single launches (f_in -> f_out, then ping-pong with the batch's
+// scratch), after two untimed steps.
+constexpr int TUNE_STEPS = 8;
+
+int time_launch(cdbm_batch* b, const void* f_in, void* f_out, hipStream_t st, double* ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int rc = CDBM_OK;
+    double best = -1.0;
+    if (e != hipSuccess) rc = hip_fail(e, "hipEventCreate");
+    for (int rep = 0; rc == CDBM_OK && rep < 4; ++rep) {
+        // rep 0 is the warm-up
+        if (rep > 0 && (e = hipEventRecord(e0, st)) != hipSuccess) {
+            rc = hip_fail(e, "hipEventRecord");
+            break;
+        }
+        const int n = rep == 0 ? 2 : TUNE_STEPS;
+        e = batch_step_once(b, f_in, f_out, st);
+        for (int k = 1; e == hipSuccess && k < n; ++k)
+            e = (k % 2) ? batch_step_once(b, f_out, b->scratch, st)
+                        : batch_step_once(b, b->scratch, f_out, st);
+        if (e != hipSuccess) {
+            rc = hip_fail(e, "batch step launch");
+            break;
+        }
+        if (rep == 0) continue;
+        float t = 0.0f;
+        if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) {
+            rc = hip_fail(e, "timing the batch step");
+            break;
+        }
+        const double per = (double)t / n;
+        if (best < 0.0 || per < best) best = per;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    *ms = best;
+    return rc;
+}
+
+int autotune(cdbm_batch* b, const void* f_in, void* f_out, const char* cache_path,
+             cdbm_batch_launch* chosen, hipStream_t st) {
+    const std::string key = tune_key(b);
+    auto ents = read_cache(cache_path);
+    for (const auto& kv : ents)
+        if (kv.first == key && check_launch(kv.second.l) == CDBM_OK) {
+            int rc = apply_launch(b, kv.second.l);
+            if (rc == CDBM_OK && chosen) *chosen = b->launch;
+            return rc;
+        }
+    // candidates: the contiguous split with three fill weights (the default
+    // first), and the row-piece form with three piece heights
+    const cdbm_batch_launch cands[] = {
+        {CDBM_BATCH_CONTIGUOUS, BATCH_FILL, 0, 0}, {CDBM_BATCH_CONTIGUOUS, 0, 0, 0},
+        {CDBM_BATCH_CONTIGUOUS, 2 * BATCH_FILL, 0, 0}, {CDBM_BATCH_ROW_PIECES, 0, 128, 0},
+        {CDBM_BATCH_ROW_PIECES, 0, 192, 0}, {CDBM_BATCH_ROW_PIECES, 0, 256, 0},
+    };
+    TuneEntry best{cands[0], -1.0};
+    for (const cdbm_batch_launch& c : cands) {
+        int rc = apply_launch(b, c);
+        double ms = 0.0;
+        if (rc == CDBM_OK) rc = time_launch(b, f_in, f_out, st, &ms);
+        if (rc != CDBM_OK) return rc;
+        if (best.ms < 0.0 || ms < best.ms) best = TuneEntry{c, ms};
+    }
+    int rc = apply_launch(b, best.l);
+    if (rc != CDBM_OK) return rc;
+    if (cache_path) {
+        ents.emplace_back(key, best);
+        write_cache(cache_path, ents);
+    }
+    if (chosen) *chosen = b->launch;
+    return CDBM_OK;
 }
 
 int check_batch_device(const cdbm_batch* b) {
@@ -120,13 +379,11 @@ int cdbm_batch_create(const cdbm_params* per_grid, int32_t ngrids, const int64_t
     b->total_elems = end;
     b->elem = b->precision == CDBM_MIXED ? sizeof(float) : sizeof(double);
 
-    std::vector<int64_t> work(ngrids + 1, 0);
     int64_t strip_rows = 0;
     for (int g = 0; g < ngrids; ++g) {
         const int tx = strip_width(b->precision);
         const int64_t strips = (per_grid[g].nx + tx - 1) / tx;
         strip_rows += strips * per_grid[g].ny;
-        work[g + 1] = work[g] + strips * (per_grid[g].ny + BATCH_FILL);
     }
     hipError_t e = hipGetDevice(&b->device);
     if (e != hipSuccess) {
@@ -144,15 +401,18 @@ int cdbm_batch_create(const cdbm_params* per_grid, int32_t ngrids, const int64_t
     if ((e = hipMemcpy(b->d_k, b->k.data(), sizeof(KParams) * ngrids, hipMemcpyHostToDevice)) !=
             hipSuccess ||
         (e = hipMemcpy(b->d_off, f_offsets, sizeof(int64_t) * ngrids, hipMemcpyHostToDevice)) !=
-            hipSuccess ||
-        (e = hipMemcpy(b->d_work, work.data(), sizeof(int64_t) * (ngrids + 1),
-                       hipMemcpyHostToDevice)) != hipSuccess) {
+            hipSuccess) {
         release(b);
         return hip_fail(e, "hipMemcpy of the batch tables");
     }
     const int64_t cap = (strip_rows + 31) / 32;
     int64_t nb = b->precision == CDBM_MIXED ? batch_blocks<float>() : batch_blocks<double>();
     b->nblocks = (int)std::max<int64_t>(1, std::min(nb, cap));
+    int rc = apply_launch(b, b->launch);
+    if (rc != CDBM_OK) {
+        release(b);
+        return rc;
+    }
     // the chunked form of the step (16-byte chunks, 32-bit offsets within a grid)
     const int cw = b->precision == CDBM_MIXED ? 4 : 2;
     const uint64_t esz = b->precision == CDBM_MIXED ? 4 : 8;
@@ -212,6 +472,27 @@ int cdbm_batch_step(cdbm_batch* b, const void* f_in, void* f_out, int32_t nsteps
         return e == hipSuccess ? CDBM_OK : hip_fail(e, "hipMemcpyAsync");
     }
     return run_steps(batch_step_once, b, f_in, f_out, b->scratch, nsteps, st, b->graph);
+}
+
+int cdbm_batch_get_launch(const cdbm_batch* b, cdbm_batch_launch* out) {
+    if (!b || !out) return fail(CDBM_EINVAL, "null argument");
+    *out = b->launch;
+    return CDBM_OK;
+}
+
+int cdbm_batch_set_launch(cdbm_batch* b, const cdbm_batch_launch* l) {
+    if (!b || !l) return fail(CDBM_EINVAL, "null argument");
+    int rc = check_batch_device(b);
+    if (rc != CDBM_OK) return rc;
+    return apply_launch(b, *l);
+}
+
+int cdbm_batch_autotune(cdbm_batch* b, const void* f_in, void* f_out, const char* cache_path,
+                        cdbm_batch_launch* chosen, void* stream) {
+    if (!b || !f_in || !f_out) return fail(CDBM_EINVAL, "null argument");
+    int rc = check_batch_device(b);
+    if (rc != CDBM_OK) return rc;
+    return autotune(b, f_in, f_out, cache_path, chosen, (hipStream_t)stream);
 }
 
 }  // extern "C"

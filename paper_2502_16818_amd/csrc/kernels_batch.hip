@@ -1,7 +1,8 @@
 // Batched ensemble step: one persistent launch advances every grid of the
-// batch by one time step.  The work of all grids is laid out as one sequence
-// of (grid, strip, row) triples (grid-major), each strip weighted by its rows
-// plus BATCH_FILL for the pipeline fill of a segment; block number L takes
+// batch by one time step, in one of two work layouts.  Contiguous form: the
+// work of all grids is laid out as one sequence of (grid, strip, row) triples
+// (grid-major), each strip weighted by its rows plus `fill` positions for the
+// pipeline fill of a segment; block number L takes
 // the L-th of gridDim.x equal contiguous pieces, so the load is balanced
 // however uneven the grids are.  Blocks are numbered XCD by XCD (the
 // hardware deals them out to the 8 XCDs in turn), so neighbouring pieces,
@@ -25,7 +26,7 @@ __global__ void __launch_bounds__(StripKernel<S>::NT) k_batch_step(const S* __re
                                                          const KParams* __restrict__ Ks,
                                                          const int64_t* __restrict__ f_off,
                                                          const int64_t* __restrict__ work_start,
-                                                         int ngrids) {
+                                                         int ngrids, int fill) {
     using SK = StripKernel<S>;
     __shared__ __attribute__((aligned(16))) S F0[SK::F0_ELEMS];
     __shared__ __attribute__((aligned(16))) S F1[SK::F1_ELEMS];
@@ -39,18 +40,72 @@ __global__ void __launch_bounds__(StripKernel<S>::NT) k_batch_step(const S* __re
     while (u < u1) {
         while (work_start[g + 1] <= u) ++g;   // grids are visited in order
         const KParams& K = Ks[g];
-        // strip s of grid g spans BATCH_FILL + ny positions: the pipeline fill
-        // of a segment, then one position per row
-        const int64_t len = (int64_t)K.ny + BATCH_FILL;
+        // strip s of grid g spans fill + ny positions: the pipeline fill of a
+        // segment, then one position per row
+        const int64_t len = (int64_t)K.ny + fill;
         const int64_t v = u - work_start[g];
         const int s = (int)(v / len);
         const int64_t p0 = (int64_t)s * len;
         const int64_t e = min(p0 + len, min(u1, work_start[g + 1]) - work_start[g]);
-        const int ya = (int)max((int64_t)0, v - p0 - BATCH_FILL);
-        const int yb = (int)max((int64_t)0, e - p0 - BATCH_FILL);
+        const int ya = (int)max((int64_t)0, v - p0 - fill);
+        const int yb = (int)max((int64_t)0, e - p0 - fill);
         if (ya < yb)
             SK::template run<VEC>(fin + f_off[g], fout + f_off[g], K, s * SK::TX, ya, yb, F0, F1);
         u = work_start[g] + e;
+    }
+}
+
+// Row-piece form.  Work units (grid g, row piece p, strip s) are numbered
+// grid by grid, piece by piece, strip by strip, so consecutive units are
+// neighbouring strips of the same rows.  The unit sequence is cut into nq
+// contiguous ranges of about equal weight (rows plus the pipeline fill), one
+// per XCD; block b (on XCD b % 8) takes the units of range b % nq in order,
+// one at a time, from that range's counter.  The blocks working at the same
+// time on one XCD then hold neighbouring strips at the same rows (their row
+// segments share DRAM pages, their halo lines that XCD's L2), and a block
+// that finishes early takes the next unit.  Every block leaves once its
+// range is used up; the last block to leave resets the counters for the
+// next launch.
+template <typename S, bool VEC>
+__global__ void __launch_bounds__(StripKernel<S>::NT) k_batch_step_rows(
+    const S* __restrict__ fin, S* __restrict__ fout, const KParams* __restrict__ Ks,
+    const int64_t* __restrict__ f_off, const int64_t* __restrict__ unit_start,
+    const int* __restrict__ geom, const int64_t* __restrict__ range_start, int nq,
+    int* __restrict__ counters) {
+    using SK = StripKernel<S>;
+    __shared__ __attribute__((aligned(16))) S F0[SK::F0_ELEMS];
+    __shared__ __attribute__((aligned(16))) S F1[SK::F1_ELEMS];
+    // the unit number is handed to the block through the first bytes of F0:
+    // the rings are idle between units (a segment ends behind a barrier after
+    // its last ring access and starts by writing F0 after the second barrier
+    // below), and the two rings fill the whole 160 KiB of LDS
+    volatile int64_t* s_u = reinterpret_cast<volatile int64_t*>(F0);
+    const int q = blockIdx.x % nq;
+    const int64_t u_end = range_start[q + 1];
+    int g = 0;
+    for (;;) {
+        if (threadIdx.x == 0) *s_u = range_start[q] + atomicAdd(&counters[q], 1);
+        __syncthreads();
+        // the same value in every lane: make it scalar, so that everything
+        // derived from it (grid, strip, rows) stays in scalar registers
+        const int64_t ul = *s_u;
+        const int64_t u =
+            (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(ul >> 32)) << 32) |
+                      (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)ul));
+        __syncthreads();   // every thread has read the unit before F0 is written again
+        if (u >= u_end) break;
+        while (unit_start[g + 1] <= u) ++g;   // a block's units only move forward
+        const int strips = geom[3 * g], rows = geom[3 * g + 2];
+        const int64_t v = u - unit_start[g];
+        const int p = (int)(v / strips), s = (int)(v - (int64_t)p * strips);
+        const KParams& K = Ks[g];
+        const int ya = p * rows, yb = min(K.ny, ya + rows);
+        SK::template run<VEC>(fin + f_off[g], fout + f_off[g], K, s * SK::TX, ya, yb, F0, F1);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&counters[nq], 1) == (int)gridDim.x - 1)
+            for (int k = 0; k <= nq; ++k) atomicExch(&counters[k], 0);
     }
 }
 
@@ -73,14 +128,30 @@ int batch_blocks() {
 
 template <typename S>
 hipError_t launch_batch_step(const void* fin, void* fout, const KParams* Ks, const int64_t* f_off,
-                             const int64_t* work_start, int ngrids, int nblocks, bool chunked,
-                             hipStream_t st) {
+                             const int64_t* work_start, int ngrids, int fill, int nblocks,
+                             bool chunked, hipStream_t st) {
     if (chunked && aligned16(fin, fout))
         hipLaunchKernelGGL((k_batch_step<S, true>), dim3(nblocks), dim3(StripKernel<S>::NT), 0, st,
-                           (const S*)fin, (S*)fout, Ks, f_off, work_start, ngrids);
+                           (const S*)fin, (S*)fout, Ks, f_off, work_start, ngrids, fill);
     else
         hipLaunchKernelGGL((k_batch_step<S, false>), dim3(nblocks), dim3(StripKernel<S>::NT), 0, st,
-                           (const S*)fin, (S*)fout, Ks, f_off, work_start, ngrids);
+                           (const S*)fin, (S*)fout, Ks, f_off, work_start, ngrids, fill);
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_batch_step_rows(const void* fin, void* fout, const KParams* Ks,
+                                  const int64_t* f_off, const int64_t* unit_start, const int* geom,
+                                  const int64_t* range_start, int nq, int* counters, int nblocks,
+                                  bool chunked, hipStream_t st) {
+    if (chunked && aligned16(fin, fout))
+        hipLaunchKernelGGL((k_batch_step_rows<S, true>), dim3(nblocks), dim3(StripKernel<S>::NT), 0,
+                           st, (const S*)fin, (S*)fout, Ks, f_off, unit_start, geom, range_start, nq,
+                           counters);
+    else
+        hipLaunchKernelGGL((k_batch_step_rows<S, false>), dim3(nblocks), dim3(StripKernel<S>::NT),
+                           0, st, (const S*)fin, (S*)fout, Ks, f_off, unit_start, geom, range_start,
+                           nq, counters);
     return hipGetLastError();
 }
 
@@ -91,8 +162,14 @@ int strip_width(int precision) {
 template int batch_blocks<float>();
 template int batch_blocks<double>();
 template hipError_t launch_batch_step<float>(const void*, void*, const KParams*, const int64_t*,
-                                             const int64_t*, int, int, bool, hipStream_t);
+                                             const int64_t*, int, int, int, bool, hipStream_t);
 template hipError_t launch_batch_step<double>(const void*, void*, const KParams*, const int64_t*,
-                                              const int64_t*, int, int, bool, hipStream_t);
+                                              const int64_t*, int, int, int, bool, hipStream_t);
+template hipError_t launch_batch_step_rows<float>(const void*, void*, const KParams*,
+                                                 const int64_t*, const int64_t*, const int*,
+                                                 const int64_t*, int, int*, int, bool, hipStream_t);
+template hipError_t launch_batch_step_rows<double>(const void*, void*, const KParams*,
+                                                  const int64_t*, const int64_t*, const int*,
+                                                  const int64_t*, int, int*, int, bool, hipStream_t);
 
 }  // namespace cdbm

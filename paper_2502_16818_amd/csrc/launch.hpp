@@ -59,12 +59,12 @@ hipError_t launch_accumulate_scalar(const double* part, int nblocks, double scal
 
 // Batched ensemble (kernels_batch.hip).  Ks: per-grid constants (device);
 // f_off: element offset of each grid's f block (device); work_start: prefix
-// sums of the grids' weighted strip counts, strips * (ny + BATCH_FILL),
+// sums of the grids' weighted strip counts, strips * (ny + fill),
 // ngrids + 1 entries (device).
 template <typename S>
 int batch_blocks();
-// Positions a strip of the batch split weighs beyond its rows: the pipeline
-// fill of a segment, in rows.
+// Positions a strip of the contiguous batch split weighs beyond its rows by
+// default: the pipeline fill of a segment, in rows.
 constexpr int BATCH_FILL = 14;
 // Output columns per strip of the fused step for a precision form.
 int strip_width(int precision);
@@ -72,7 +72,18 @@ int strip_width(int precision);
 // 16-byte chunk (the buffers' alignment is checked at launch).
 template <typename S>
 hipError_t launch_batch_step(const void* fin, void* fout, const KParams* Ks, const int64_t* f_off,
-                             const int64_t* work_start, int ngrids, int nblocks, bool chunked,
-                             hipStream_t st);
+                             const int64_t* work_start, int ngrids, int fill, int nblocks,
+                             bool chunked, hipStream_t st);
+
+// Row-piece form of the batched step: unit_start (ngrids + 1, device):
+// prefix sums of the grids' units (strips x row pieces); geom (3 ngrids,
+// device): strips, pieces and rows per piece of each grid; range_start
+// (nq + 1, device): the unit ranges of the nq counters; counters (nq + 1
+// ints, device, zero before the first launch; the kernel leaves them zero).
+template <typename S>
+hipError_t launch_batch_step_rows(const void* fin, void* fout, const KParams* Ks,
+                                  const int64_t* f_off, const int64_t* unit_start, const int* geom,
+                                  const int64_t* range_start, int nq, int* counters, int nblocks,
+                                  bool chunked, hipStream_t st);
 
 }  // namespace cdbm

@@ -128,3 +128,84 @@ def test_batched_ensemble_workload_runs_and_conserves_mass():
     for k in range(len(runs)):
         m1 = b.view(out, k).double().sum().item()
         assert abs(m1 - m0[k]) <= 2e-6 * abs(m0[k])
+
+
+LAYOUTS = {"contiguous_fill0": (0, 0, 0), "contiguous_fill28": (0, 28, 0),
+           "rows16": (1, 0, 16), "rows96": (1, 0, 96), "rows384": (1, 0, 384)}
+
+
+@pytest.mark.parametrize("layout", sorted(LAYOUTS))
+@pytest.mark.parametrize("sizes", sorted(SIZE_SETS))
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_batch_layouts_are_bitwise_equal(precision, sizes, layout):
+    """Every launch layout gives the default layout's result bit for bit,
+    over a run long enough to replay the captured graph twice (the row-piece
+    form's counters must be back at zero after every launch)."""
+    from paper_2502_16818_amd import Batch
+    runs = _mixed_set(sizes)
+    b = Batch(_params(runs, precision))
+    f = b.init([(r.rho, r.ux, r.uy, r.T) for r in runs])
+    ref = b.step(f, nsteps=67)
+    lay, fill, rows = LAYOUTS[layout]
+    b.set_launch(lay, fill, rows)
+    assert b.get_launch() == {"layout": lay, "fill_rows": fill, "piece_rows": rows}
+    for rep in range(2):
+        out = b.step(f, nsteps=67)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+    b.close()
+
+
+def test_batch_rejects_bad_layouts():
+    from paper_2502_16818_amd import Batch, CdbmError
+    b = Batch(_params(_mixed_set()[:2], FP64))
+    for bad in ((2, 14, 0), (0, -1, 0), (0, 2000, 0), (1, 0, 8), (1, 0, 100000)):
+        with pytest.raises(CdbmError) as e:
+            b.set_launch(*bad)
+        assert e.value.code == -1
+    assert b.get_launch()["layout"] == 0
+    b.close()
+
+
+def test_autotuned_ensemble_is_no_slower_than_the_default(tmp_path):
+    """The tuner on the 96-grid ensemble (mixed): its choice is the fastest of
+    its timed candidates, among them the default contiguous split, so it must
+    not run slower than the default (5 % timing noise allowed); its result
+    stays bitwise that of the default; a second tuner call finds the JSON
+    cache entry and applies it without timing."""
+    import json
+    from paper_2502_16818_amd import Batch
+    runs = W.batched_ensemble()
+    b = Batch(_params(runs, MIXED))
+    f = b.init([(r.rho, r.ux, r.uy, r.T) for r in runs])
+    ref = b.step(f, nsteps=5)
+
+    def ms_per_step(n=40):
+        out = b.empty_f()
+        b.step(f, out, nsteps=8)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.step(f, out, nsteps=n)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    t_default = ms_per_step()
+    cache = str(tmp_path / "tune.json")
+    chosen = b.autotune(f, b.empty_f(), cache)
+    t_tuned = ms_per_step()
+    print(f"  default {t_default:.4f} ms/step, tuned {chosen} {t_tuned:.4f} ms/step")
+    assert t_tuned <= 1.05 * t_default
+    assert torch.equal(b.step(f, nsteps=5), ref)
+    entries = json.load(open(cache))
+    assert len(entries) == 1
+    (key, val), = entries.items()
+    assert key.split("|")[1] == "mixed"
+    assert {k: val[k] for k in ("layout", "fill_rows", "piece_rows")} == chosen
+    # a new batch of the same key takes the cached layout
+    b2 = Batch(_params(runs, MIXED))
+    assert b2.autotune(f, b2.empty_f(), cache) == chosen
+    assert b2.get_launch() == chosen
+    b.close()
+    b2.close()
