@@ -321,10 +321,11 @@ SOD_SHOCK_SPEED = 1.752156
 
 def tube_and_vortex_runs():
     """The paper-shaped runs beside the headline: the 500 x 1 Sod tube (FP64,
-    5000 steps to t = 0.1) and the 512 x 512 Taylor-Green vortex (10000 steps
-    to t = 1, FP64 and mixed).  Reports time per step, the Sod shock position
-    against the exact one and the vortex's kinetic-energy decay against
-    exp(-4 nu t), nu = T tau."""
+    5000 steps to t = 0.1), the 512 x 512 Taylor-Green vortex (10000 steps
+    to t = 1, FP64 and mixed) and the Sec. 3.4 sound wave's Mach cone (both
+    forms).  Reports time per step, the Sod shock position against the exact
+    one, the vortex's kinetic-energy decay against exp(-4 nu t), nu = T tau,
+    and the cone's sin(theta) against 1/2."""
     import numpy as np
     import torch
     import workloads as W
@@ -375,7 +376,41 @@ def tube_and_vortex_runs():
     tg["mixed_vs_fp64_ux_rel_l2"] = float(diff)
     tg["steps"] = W.taylor_green_2pi().steps
     out["taylor_green_512"] = tg
+    out["sound_wave_1600x1200"] = {"fp64": sound_wave_run(FP64), "mixed": sound_wave_run(MIXED),
+                                   "paper": {"sin_theta": 0.50106, "relative_error": 0.00212}}
     return out
+
+
+def sound_wave_run(precision):
+    """The Sec. 3.4 sound wave (1600 x 1200 cells, 10000 steps to t = 0.2) with
+    the moving source of workloads.sound_wave_source added between steps;
+    returns the cone's sin(theta) and the time per step (source included)."""
+    import torch
+    import workloads as W
+    from paper_2502_16818_amd import Solver, make_params
+    run = W.sound_wave_cone()
+    src = W.sound_wave_source(run)
+    s = Solver.from_run(run, precision)
+    f = s.init(run.rho, run.ux, run.uy, run.T)
+    one = Solver(make_params(1, 1, run.dx, run.dy, run.dt, run.tau, run.gamma, run.v, run.eta,
+                             run.bc_x, run.bc_y, precision))
+    w = one.init([[1.0]], [[0.0]], [[0.0]], [[1.0]]).reshape(16, 1, 1)
+    one.close()
+    g = s.empty_f()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(run.steps):
+        xs, ys, dens = src.window(run, n * run.dt)
+        f[:, ys, xs] += w * torch.as_tensor(dens * run.dt, dtype=s.dtype, device="cuda")[None]
+        s.step(f, g, nsteps=1)
+        f, g = g, f
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    drho = s.moments(f)[0].cpu().numpy() - 1.0
+    s.close()
+    sin_t, _, _ = W.cone_sin_theta(drho, run, src, run.steps * run.dt)
+    return {"sin_theta": sin_t, "exact": 0.5, "relative_error": abs(sin_t - 0.5) / 0.5,
+            "ms_per_step_with_source": el * 1e3 / run.steps, "steps": run.steps}
 
 
 def run_full_seed(run):

@@ -179,6 +179,104 @@ def taylor_green_2pi(n: int = 512, U0: float = 0.1, tau: float = 1e-4, dt: float
                steps, rho, ux, uy, p / rho)
 
 
+def sound_wave_cone(nx: int = 1600, ny: int = 1200, dx: float = 5e-4, dt: float = 2e-5,
+                    tau: float = 1e-4, gamma: float = 1.4, t_end: float = 0.2) -> Run:
+    """The Sec. 3.4 two-dimensional sound wave: 1600 x 1200 cells of 5e-4,
+    dt = 2e-5, tau = 1e-4, gamma = 1.4, Sec. 3.4 velocity set, to t = 0.2.
+
+    The paper states neither the background nor the source.  Reading: gas at
+    rest with rho = 1 and T = 1 (so that its kinematic viscosity T tau is the
+    1e-4 it quotes), zero-gradient sides, and a perturbation that is
+    introduced continuously at a point moving to the right at twice the
+    sound speed from x0 (see SoundSource); the disturbance it leaves spreads
+    at the sound speed, so its envelope is a cone of half-angle theta with
+    sin(theta) = 1/2."""
+    v, eta = VELOCITY_SETS["sound"]
+    one = np.ones((ny, nx))
+    return Run("sound_wave_cone", nx, ny, dx, dx, dt, tau, gamma, v, eta, ZERO_GRADIENT,
+               ZERO_GRADIENT, int(round(t_end / dt)), one, 0.0 * one, 0.0 * one, one.copy())
+
+
+@dataclasses.dataclass
+class SoundSource:
+    """A moving point source of equilibrium gas at rest (a density pulse at
+    the background temperature): at time t it adds, per unit time,
+    rate * exp(-|r - r_s(t)|^2 / (2 width^2)) of density at the cells within
+    4 widths of r_s(t) = (x0 + speed t, y0).  The velocity-space shape of the
+    added gas is the equilibrium of the background state, which each side
+    computes with its own equilibrium."""
+
+    x0: float
+    y0: float
+    speed: float
+    width: float
+    rate: float
+
+    def window(self, run: Run, t: float):
+        """Cell ranges (x slice, y slice) and the density added per unit time
+        on them at time t, as a (ny_w, nx_w) float64 array."""
+        xs = self.x0 + self.speed * t
+        r = 4.0 * self.width
+        i0 = max(0, int(np.floor((xs - r) / run.dx)))
+        i1 = min(run.nx, int(np.ceil((xs + r) / run.dx)) + 1)
+        j0 = max(0, int(np.floor((self.y0 - r) / run.dy)))
+        j1 = min(run.ny, int(np.ceil((self.y0 + r) / run.dy)) + 1)
+        x = (np.arange(i0, i1) + 0.5) * run.dx
+        y = (np.arange(j0, j1) + 0.5) * run.dy
+        X, Y = np.meshgrid(x, y, indexing="xy")
+        g = self.rate * np.exp(-((X - xs) ** 2 + (Y - self.y0) ** 2) / (2 * self.width ** 2))
+        return slice(i0, i1), slice(j0, j1), g
+
+
+def sound_wave_source(run: Run, mach: float = 2.0, x0_frac: float = 0.3125,
+                      width_cells: float = 4.0, rate: float = 1.0) -> SoundSource:
+    """The moving source of sound_wave_cone: speed mach * sqrt(gamma T) with
+    T = 1, starting at x0 = x0_frac * Lx (0.25 of the 0.8-long domain, so
+    that the first disturbance stays inside it until t = 0.2) on the
+    mid-line."""
+    c = math.sqrt(run.gamma * 1.0)
+    return SoundSource(x0_frac * run.nx * run.dx, 0.5 * run.ny * run.dy, mach * c,
+                       width_cells * run.dx, rate)
+
+
+def cone_sin_theta(drho: np.ndarray, run: Run, src: SoundSource, t: float,
+                   d_range=(0.06, 0.30)):
+    """Half-angle of the Mach cone in a density perturbation field drho
+    (ny, nx) at time t.  In every column between d_range[0] and d_range[1]
+    behind the apex x0 + speed t, on each side of the mid-line, the Mach wave
+    is the largest value of drho; its position is refined to a fraction of a
+    cell by the parabola through that cell and its two neighbours.  A
+    straight line fitted to those positions on each side gives tan(theta).
+    (The outer edge of the disturbance, say where drho falls to half its
+    peak, lies further out the older the wave is, as the wave spreads; the
+    peak does not move with the spreading.)  Returns (sin(theta), per-side
+    tan(theta), number of columns).  Field analysis only: no arithmetic of
+    the method."""
+    xa = src.x0 + src.speed * t
+    x = (np.arange(run.nx) + 0.5) * run.dx
+    y = (np.arange(run.ny) + 0.5) * run.dy
+    cols = np.nonzero((xa - x >= d_range[0]) & (xa - x <= d_range[1]))[0]
+    jm = int(np.searchsorted(y, src.y0))
+    slopes = []
+    for side in (1, -1):
+        xs, ys = [], []
+        for i in cols:
+            col = drho[jm:, i] if side > 0 else drho[jm - 1::-1, i]
+            yy = y[jm:] if side > 0 else y[jm - 1::-1]
+            k = int(np.argmax(col))
+            if k == 0 or k + 1 >= col.size:
+                continue
+            a, b, c = col[k - 1], col[k], col[k + 1]
+            den = a - 2.0 * b + c
+            off = 0.5 * (a - c) / den if den != 0.0 else 0.0
+            ys.append(yy[k] + off * (yy[k + 1] - yy[k]))
+            xs.append(x[i])
+        slope = np.polyfit(np.asarray(xs), np.abs(np.asarray(ys) - src.y0), 1)[0]
+        slopes.append(float(-slope))
+    tan = float(np.mean(slopes))
+    return tan / math.sqrt(1.0 + tan * tan), slopes, int(len(cols))
+
+
 HEADLINE_GAMMAS = (1.2, 1.4, 5.0 / 3.0)
 
 # Velocity set of the headline workload per specific-heat ratio: the Sec. 3.2
