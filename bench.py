@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-paper-runs", action="store_true",
                     help="skip the Sod tube and Taylor-Green runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm-floor", type=float, default=1.0,
+                    help="least seconds of untimed stepping before each timed region")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the mixed-against-FP64 error runs at full run lengths")
     ap.add_argument("--cpu-sample", type=int, default=1024, help="grid side of the oracle sample")
@@ -138,7 +140,7 @@ def time_steps(solver, f_a, f_b, steps, warmup):
     on the stream the library launches on (torch's current stream), after
     warm_up."""
     import torch
-    warm_up(solver, f_a, f_b, warmup)
+    warm_up(solver, f_a, f_b, warmup, WARM_FLOOR_S)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -419,6 +421,8 @@ def run_full_seed(run):
 
 def main():
     args = parse()
+    global WARM_FLOOR_S
+    WARM_FLOOR_S = args.warm_floor
     if args.traffic_from:
         import workloads as W
         record_traffic(*args.traffic_from, W.headline(seed=args.seed, n=args.n).name)
