@@ -54,7 +54,7 @@ enum {
 
 enum { CDBM_PERIODIC = 0, CDBM_ZERO_GRADIENT = 1 };
 enum { CDBM_FP64 = 0, CDBM_MIXED = 1 };
-enum { CDBM_STEP_AUTO = 0, CDBM_STEP_FUSED = 1, CDBM_STEP_SPLIT = 2 };
+enum { CDBM_STEP_AUTO = 0, CDBM_STEP_FUSED = 1, CDBM_STEP_SPLIT = 2, CDBM_STEP_FUSED2 = 3 };
 
 /* Run parameters (Secs. 2 and 3).
  *   nx, ny      grid cells (ny = 1 for a tube); 1 <= nx, ny <= 65536 and
@@ -83,7 +83,12 @@ enum { CDBM_STEP_AUTO = 0, CDBM_STEP_FUSED = 1, CDBM_STEP_SPLIT = 2 };
  *               grids, where the fused launch has too few strips to fill the
  *               chip).  CDBM_STEP_AUTO: split up to 2^19 cells (724 x 724)
  *               in the mixed form and 2^18 (512 x 512) in FP64, fused
- *               above.  Ignored by the batched form (always fused).
+ *               above.  CDBM_STEP_FUSED2 (CDBM_MIXED only): two time steps
+ *               per launch (temporal blocking: f crosses HBM once in and
+ *               once out per two steps, on 48-column strips that carry four
+ *               rings of stages in LDS); an odd last step runs fused.  Same
+ *               results as CDBM_STEP_FUSED bit for bit.  Ignored by the
+ *               batched form (always fused).
  *   dof_given   0: the gas is given by gamma.  1: it is given by the extra
  *               degrees of freedom `extra_dof` = I >= 0 of Eq. (5) (finite),
  *               and gamma is ignored.  A zero-initialised struct selects

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libcdbm.so")
 OK, EINVAL, ESINGULAR, ENONPHYS, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5
 PERIODIC, ZERO_GRADIENT = 0, 1
 FP64, MIXED = 0, 1
-STEP_AUTO, STEP_FUSED, STEP_SPLIT = 0, 1, 2
+STEP_AUTO, STEP_FUSED, STEP_SPLIT, STEP_FUSED2 = 0, 1, 2, 3
 
 EXPORTS = (
     "cdbm_last_error", "cdbm_create", "cdbm_destroy", "cdbm_get_params", "cdbm_init",

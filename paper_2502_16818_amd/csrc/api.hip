@@ -213,6 +213,12 @@ hipError_t step_single(const void* ctx, const void* fin, void* fout, hipStream_t
     return step_once((const cdbm_handle*)ctx, fin, fout, st);
 }
 
+// two time steps in one launch (CDBM_STEP_FUSED2)
+hipError_t step_pair(const void* ctx, const void* fin, void* fout, hipStream_t st) {
+    const cdbm_handle* h = (const cdbm_handle*)ctx;
+    return launch_step2_fused(fin, fout, h->k, h->kdev, st);
+}
+
 }  // namespace
 }  // namespace cdbm
 
@@ -247,8 +253,9 @@ int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
     h->split = p->step_form == CDBM_STEP_SPLIT ||
                (p->step_form == CDBM_STEP_AUTO &&
                 h->cells <= (mixed(h) ? SPLIT_STEP_CELLS_MIXED : SPLIT_STEP_CELLS_FP64));
+    h->two = p->step_form == CDBM_STEP_FUSED2;
     if (ensure_buffer(h, &h->scratch) != CDBM_OK ||
-        (h->split && ensure_buffer(h, &h->stage) != CDBM_OK) ||
+        ((h->split || h->two) && ensure_buffer(h, &h->stage) != CDBM_OK) ||
         hipMalloc(&h->partials, sizeof(double) * 4 * REDUCE_BLOCKS) != hipSuccess ||
         hipMalloc(&h->tau_part, sizeof(double) * tau_blocks) != hipSuccess ||
         hipMalloc(&h->flag, sizeof(int)) != hipSuccess ||
@@ -311,6 +318,20 @@ int cdbm_step(cdbm_handle* h, const void* f_in, void* f_out, int32_t nsteps, voi
     if (nsteps == 0) {
         hipError_t e = hipMemcpyAsync(f_out, f_in, h->fbytes, hipMemcpyDeviceToDevice, st);
         return e == hipSuccess ? CDBM_OK : hip_fail(e, "hipMemcpyAsync");
+    }
+    if (h->two) {
+        // pairs of steps per launch; an odd last step runs fused, from the
+        // pairs' result in the handle's stage buffer
+        const int pairs = nsteps / 2;
+        if (nsteps % 2 == 0) return run_steps(step_pair, h, f_in, f_out, h->scratch, pairs, st, h->graph);
+        const void* src = f_in;
+        if (pairs > 0) {
+            rc = run_steps(step_pair, h, f_in, h->stage, h->scratch, pairs, st, h->graph);
+            if (rc != CDBM_OK) return rc;
+            src = h->stage;
+        }
+        hipError_t e = launch_step_fused<float>(src, f_out, h->k, h->kdev, st);
+        return e == hipSuccess ? CDBM_OK : hip_fail(e, "step launch");
     }
     return run_steps(step_single, h, f_in, f_out, h->scratch, nsteps, st, h->graph);
 }

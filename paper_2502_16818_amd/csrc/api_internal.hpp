@@ -55,6 +55,7 @@ struct cdbm_handle {
     void* scratch = nullptr;    // f-sized ping-pong buffer
     void* stage = nullptr;      // f-sized buffer of a stage-1 state (adjoint, split steps)
     bool split = false;         // step as two single-stage launches (small grids)
+    bool two = false;           // two steps per launch (CDBM_STEP_FUSED2)
     void* lam_mid = nullptr;    // f-sized buffer for the adjoint's intermediate product
     double* partials = nullptr; // reduction partials
     double* tau_part = nullptr; // per-block partial sums of the adjoint's tau term (two stages)

@@ -38,6 +38,10 @@ template <typename S>
 hipError_t launch_step_fused(const void* fin, void* fout, const KParams& K, const KParams* Kd,
                              hipStream_t st);
 
+// Two fused steps in one launch, FP32 storage (kernels_step.hip, step_two.hpp).
+hipError_t launch_step2_fused(const void* fin, void* fout, const KParams& K, const KParams* Kd,
+                              hipStream_t st);
+
 // Adjoint (kernels_adjoint.hip).  tau_part: one double per block
 // (stage_adjoint_blocks), the block sums of the launch's tau term.
 int stage_adjoint_blocks(const KParams& K);

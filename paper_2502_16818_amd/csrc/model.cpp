@@ -134,8 +134,13 @@ int build_params(const cdbm_params& p, KParams& k, std::string& err) {
         err = "precision must be CDBM_FP64 or CDBM_MIXED";
         return CDBM_EINVAL;
     }
-    if (p.step_form < CDBM_STEP_AUTO || p.step_form > CDBM_STEP_SPLIT) {
-        err = "step_form must be CDBM_STEP_AUTO, CDBM_STEP_FUSED or CDBM_STEP_SPLIT";
+    if (p.step_form < CDBM_STEP_AUTO || p.step_form > CDBM_STEP_FUSED2) {
+        err = "step_form must be CDBM_STEP_AUTO, CDBM_STEP_FUSED, CDBM_STEP_SPLIT or "
+              "CDBM_STEP_FUSED2";
+        return CDBM_EINVAL;
+    }
+    if (p.step_form == CDBM_STEP_FUSED2 && p.precision != CDBM_MIXED) {
+        err = "CDBM_STEP_FUSED2 needs CDBM_MIXED: four rings of FP64 rows do not fit the LDS";
         return CDBM_EINVAL;
     }
 

@@ -138,3 +138,10 @@ def test_binding_checks_buffers_before_the_call():
     with pytest.raises(ValueError, match="device tensors"):
         B._ptr(t)
     assert B._ptr(None) is None
+
+
+def test_two_step_form_needs_fp32_storage(lib):
+    p = _params(step_form=3, precision=0)
+    h = ctypes.c_void_p()
+    assert lib.cdbm_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    assert b"CDBM_STEP_FUSED2" in lib.cdbm_last_error()
