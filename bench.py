@@ -68,6 +68,9 @@ def parse():
                          "--pmc runs (FETCH_SIZE, then WRITE_SIZE) of a --calibrate-copy bench, "
                          "scale each counter by the plain copy's reading and record the fused "
                          "step's HBM bytes per launch for the roofline's traffic field")
+    ap.add_argument("--trace-from", metavar="KERNEL_TRACE_CSV",
+                    help="no GPU work: print per-kernel launch statistics of a rocprofv3 "
+                         "--kernel-trace CSV, split by launch grid, as a markdown table")
     return ap.parse_args()
 
 
@@ -107,6 +110,53 @@ def record_traffic(fetch_csv, write_csv, workload):
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
+
+
+def short_kernel_name(name):
+    """`void ns::(anonymous namespace)::k<float, true>(args)` -> `k<float, true>`."""
+    name = name.removeprefix("void ").replace("cdbm::(anonymous namespace)::", "")
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def trace_summary(trace_csv, min_share=1e-3):
+    """Duration statistics per kernel and launch shape from a rocprofv3
+    --kernel-trace CSV.  One kernel launched on grids of different sizes (the
+    headline grid and the smaller paper runs share the step kernels) gets one
+    row per grid, so the headline launches can be read apart."""
+    import csv
+    groups = {}
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            grid = 1
+            for ax in "XYZ":
+                grid *= int(r.get(f"Grid_Size_{ax}") or 1)
+            wg = 1
+            for ax in "XYZ":
+                wg *= int(r.get(f"Workgroup_Size_{ax}") or 1)
+            key = (short_kernel_name(r["Kernel_Name"]), grid // max(wg, 1), wg)
+            d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+            g = groups.setdefault(key, [0, 0.0, float("inf"), 0.0])
+            g[0] += 1
+            g[1] += d
+            g[2] = min(g[2], d)
+            g[3] = max(g[3], d)
+    total = sum(g[1] for g in groups.values())
+    print("| kernel | workgroups x threads | calls | average (us) | min (us) | max (us) "
+          "| share of GPU time |")
+    print("|---|---|---|---|---|---|---|")
+    for (name, nwg, wg), (n, tot, lo, hi) in sorted(groups.items(), key=lambda kv: -kv[1][1]):
+        if tot < min_share * total:
+            continue
+        print(f"| `{name}` | {nwg} x {wg} | {n} | {tot / n:.1f} | {lo:.1f} | {hi:.1f} "
+              f"| {100 * tot / total:.2f} % |")
 
 
 # Least wall time spent stepping before a timed region, whatever --warmup
@@ -427,6 +477,9 @@ def main():
     if args.traffic_from:
         import workloads as W
         record_traffic(*args.traffic_from, W.headline(seed=args.seed, n=args.n).name)
+        return
+    if args.trace_from:
+        trace_summary(args.trace_from)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
