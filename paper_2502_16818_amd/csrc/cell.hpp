@@ -172,12 +172,23 @@ __device__ __forceinline__ void nonequilibrium(const Parity& g, const Macro& m, 
     // group of each parity component (k = 2 for a and c, 4 for b and d):
     // ee (a, a, b, c, c, d), oe/eo (a, b, c, d), oo (b, d)
     double tee[6], toe[4], teo[4], too[2];
+    // even-even block in mirror form (KParams::eep, ees): the rows of a
+    // mirrored pair of unknowns share their part even in x <-> y, and the
+    // constant term (mee[0] = 1) goes onto g first
+    const double s23 = mee[2] + mee[3], d23 = mee[2] - mee[3];
+    const double s45 = mee[4] + mee[5], d45 = mee[4] - mee[5];
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-        double s = K.iee[r][z];
-#pragma unroll
-        for (int c = 1; c < 6; ++c) s = fma(K.iee[r][c + z], mee[c], s);
-        tee[r] = fma((r == 2 || r == 5) ? n4 : n2, s, g.ee[r]);
+    for (int q = 0; q < 2; ++q) {
+        const int r0 = 3 * q;   // pair (r0, r0 + 1), axis groups: n2
+        const double P =
+            fma(K.eep[q][3 + z], s45, fma(K.eep[q][2 + z], s23, K.eep[q][1 + z] * mee[1]));
+        const double Q = fma(K.eep[q][5 + z], d45, K.eep[q][4 + z] * d23);
+        tee[r0] = fma(n2, P + Q, fma(n2, K.eep[q][z], g.ee[r0]));
+        tee[r0 + 1] = fma(n2, P - Q, fma(n2, K.eep[q][z], g.ee[r0 + 1]));
+        const int rd = 3 * q + 2;   // diagonal groups: n4
+        const double D =
+            fma(K.ees[q][3 + z], s45, fma(K.ees[q][2 + z], s23, K.ees[q][1 + z] * mee[1]));
+        tee[rd] = fma(n4, D, fma(n4, K.ees[q][z], g.ee[rd]));
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

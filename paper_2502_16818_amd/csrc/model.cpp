@@ -218,6 +218,41 @@ int build_params(const cdbm_params& p, KParams& k, std::string& err) {
     if ((rc = block(4, reo, ceo, soe, &k.ieo[0][0], "even-odd")) != CDBM_OK) return rc;
     if ((rc = block(2, roo, coo, soo, &k.ioo[0][0], "odd-odd")) != CDBM_OK) return rc;
 
+    // Mirror form of the even-even block (KParams::eep, ees); the x <-> y
+    // symmetry it relies on holds for every velocity set of this model, so a
+    // failure here is an internal error.
+    {
+        double scale = 0.0;
+        for (int r = 0; r < 6; ++r)
+            for (int c = 0; c < 6; ++c) scale = std::fmax(scale, std::fabs(k.iee[r][c]));
+        static const int swap[6] = {0, 1, 3, 2, 5, 4};
+        bool ok = true;
+        for (int c = 0; c < 6; ++c) {
+            ok = ok && std::fabs(k.iee[1][c] - k.iee[0][swap[c]]) <= 1e-12 * scale;
+            ok = ok && std::fabs(k.iee[4][c] - k.iee[3][swap[c]]) <= 1e-12 * scale;
+            ok = ok && std::fabs(k.iee[2][c] - k.iee[2][swap[c]]) <= 1e-12 * scale;
+            ok = ok && std::fabs(k.iee[5][c] - k.iee[5][swap[c]]) <= 1e-12 * scale;
+        }
+        if (!ok) {
+            err = "internal: even-even block is not symmetric under x <-> y";
+            return CDBM_EINVAL;
+        }
+        for (int q = 0; q < 2; ++q) {
+            const double* B = k.iee[3 * q];
+            k.eep[q][0] = B[0];
+            k.eep[q][1] = B[1];
+            k.eep[q][2] = 0.5 * (B[2] + B[3]);
+            k.eep[q][3] = 0.5 * (B[4] + B[5]);
+            k.eep[q][4] = 0.5 * (B[2] - B[3]);
+            k.eep[q][5] = 0.5 * (B[4] - B[5]);
+            const double* D = k.iee[3 * q + 2];
+            k.ees[q][0] = D[0];
+            k.ees[q][1] = D[1];
+            k.ees[q][2] = D[2];
+            k.ees[q][3] = D[4];
+        }
+    }
+
     for (int c = 0; c < 4; ++c) {
         k.jx[c] = M0[1][coe[c]];
         k.jy[c] = M0[2][ceo[c]];

@@ -42,6 +42,16 @@ struct KParams {
     double ioe[4][4];
     double ieo[4][4];
     double ioo[2][2];
+    // The even-even block in mirror form.  The velocity set is symmetric under
+    // x <-> y, which swaps unknowns 0 <-> 1 and 3 <-> 4 of the block (the
+    // axis pairs of groups a and c), keeps 2 and 5 (the diagonal groups), and
+    // swaps moments 2 <-> 3 and 4 <-> 5; so row 1 of iee is row 0 with those
+    // columns swapped, row 4 likewise row 3, and rows 2 and 5 weigh each
+    // swapped pair equally.  eep[p] (pairs p = 0: rows 0, 1; p = 1: rows 3, 4)
+    // holds {B0, B1, (B2 + B3) / 2, (B4 + B5) / 2, (B2 - B3) / 2, (B4 - B5) / 2}
+    // of the pair's first row B, and ees[p] (rows 2, 5) {B0, B1, B2, B4}.
+    double eep[2][6];
+    double ees[2][4];
     // Rows of M0 in the parity basis that give the conserved moments:
     // j_x = sum jx[k] g_oe[k], j_y = sum jy[k] g_eo[k], 2E = sum en[k] g_ee[k]
     // (rho = sum of the six even-even combinations).

@@ -212,6 +212,31 @@ struct Chunk<double> {
     typedef double type __attribute__((ext_vector_type(2)));
 };
 
+// Stores the 16 velocities of one cell, v[i] at byte offset xo + i * plane
+// from `row`, through a raw buffer descriptor: the row start and the plane
+// offsets are wave-uniform (scalar registers) and the column offset xo is the
+// only vector operand, so the stores take no per-velocity address
+// arithmetic on the vector unit.  `row` must be wave-uniform and every offset
+// below 2^32, which the chunked form guarantees (at most 4 GiB per grid).
+// Word 3 of the descriptor is the 32-bit data format of the gfx9 family.
+// (Used by the FP64 strip: in the FP32 strips the same stores measured
+// slightly slower than 64-bit addresses.)
+__device__ __forceinline__ void store_planes(double* row, uint32_t plane, uint32_t xo,
+                                             const double v[NV]) {
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, -1, 0x00020000);
+    // plane offsets formed here, one scalar add each: hoisted out of the
+    // caller's loop they would take 16 scalar registers for its whole length
+    const uint32_t step = plane + (uint32_t)opaque_zero();
+    uint32_t so = 0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[i]), rs, (int)xo, (int)so,
+                                              0);
+        so += step;
+    }
+}
+
 // Elements per 16-byte chunk of the chunked form.
 template <typename S>
 constexpr int fused_chunk_elems() {
@@ -391,9 +416,16 @@ __device__ __forceinline__ void fused_strip(const S* __restrict__ fin, S* __rest
             for (int i = 0; i < NV; ++i) materialize(out[i]);
             if (keep && ccol < TX && x < nx) {
                 const S* fn = F0 + slot(q2) * NV * W0 + 4 + ccol;   // f^n of the cell
-                S* dst = fout + (int64_t)r2 * nx + x;
 #pragma unroll
-                for (int i = 0; i < NV; ++i) dst[(int64_t)i * cells] = fma(S(0.5), fn[i * W0], out[i]);
+                for (int i = 0; i < NV; ++i) out[i] = fma(S(0.5), fn[i * W0], out[i]);
+                if constexpr (VEC) {
+                    store_planes(fout + (int64_t)r2 * nx, (uint32_t)(cells * (int64_t)sizeof(S)),
+                                 (uint32_t)x * (uint32_t)sizeof(S), out);
+                } else {
+                    S* dst = fout + (int64_t)r2 * nx + x;
+#pragma unroll
+                    for (int i = 0; i < NV; ++i) dst[(int64_t)i * cells] = out[i];
+                }
             }
         }
     }
