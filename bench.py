@@ -115,6 +115,8 @@ def record_traffic(fetch_csv, write_csv, workload):
 def short_kernel_name(name):
     """`void ns::(anonymous namespace)::k<float, true>(args)` -> `k<float, true>`."""
     name = name.removeprefix("void ").replace("cdbm::(anonymous namespace)::", "")
+    if "::" in name.split("<")[0]:   # a library's kernel: its qualified name only
+        return name.split("<")[0].split("(")[0]
     depth = 0
     for i, ch in enumerate(name):
         if ch == "<":
