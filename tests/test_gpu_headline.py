@@ -124,3 +124,30 @@ def test_largest_grids_sampled_cells_match_oracle(precision, nx, ny):
     c = max(_check_column(run, f0, f1, x, precision) for x in (1, 120, nx - 2))
     print(f"  {len(cells)} cells: worst relative error {e:.2e}; 3 full columns {c:.2e}")
     s.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", [FP64, MIXED], ids=["fp64", "mixed"])
+def test_headline_full_size_run_matches_single_steps_and_oracle(precision):
+    """The launch path the benchmark times: 36 steps in one call (two direct
+    launches, a 32-step graph replay, two more launches) equal 36 single-step
+    calls bit for bit, and the 36th step matches the oracle's step from the
+    35th state on the sampled cells and full columns."""
+    from paper_2502_16818_amd import Solver
+    run = W.headline(seed=1)
+    print(f"[case] {run.name} {run.nx}x{run.ny} precision={precision} 36-step run", flush=True)
+    s = Solver.from_run(run, precision)
+    f0 = s.init(run.rho, run.ux, run.uy, run.T)
+    many = s.step(f0, nsteps=36)
+    prev = f0
+    for _ in range(35):
+        prev = s.step(prev)
+    last = s.step(prev)
+    torch.cuda.synchronize()
+    assert torch.equal(many, last)
+    rng = np.random.default_rng(36)
+    cells = _sample_cells(run.nx, run.ny, rng)
+    e = _check_step(run, prev, last, cells, precision)
+    c = max(_check_column(run, prev, last, x, precision) for x in FULL_COLUMNS)
+    print(f"  step 36: {len(cells)} cells worst relative error {e:.2e}; full columns {c:.2e}")
+    s.close()
