@@ -81,77 +81,87 @@ struct Quad {
 };
 
 // (d f^eq / d q)^T a for q = (rho, u_x, u_y, T) at the state m, from the
-// parity transform hb = P^T a of a.
+// parity transform hb = P^T a of a: w = B^T hb and its products with the
+// raw moments and their derivatives, one parity block at a time (ee, then oe
+// and eo, then oo) with the scheduler kept from interleaving the blocks, so
+// that only one block's weights and tables are live at once.
 __device__ __forceinline__ Quad equilibrium_vjp_q_parity(const Macro& m, const KParams& K,
                                                         double a, const Parity& hb) {
-    // w = B^T hb per block
-    double wee[6], woe[4], weo[4], woo[2];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        double s = 0.0;
-#pragma unroll
-        for (int r = 0; r < 6; ++r) s = fma(K.iee[r][c], hb.ee[r], s);
-        wee[c] = s;
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        double so = 0.0, se = 0.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            so = fma(K.ioe[r][c], hb.oe[r], so);
-            se = fma(K.ieo[r][c], hb.eo[r], se);
-        }
-        woe[c] = so;
-        weo[c] = se;
-    }
-#pragma unroll
-    for (int c = 0; c < 2; ++c) woo[c] = fma(K.ioo[0][c], hb.oo[0], K.ioo[1][c] * hb.oo[1]);
-
     const double ux = m.ux, uy = m.uy, T = m.T;
     const double ux2 = ux * ux, uy2 = uy * uy, u2 = ux2 + uy2, uxy = ux * uy;
     const double A2 = u2 + (a + 2.0) * T, A4 = u2 + (a + 4.0) * T;
-    // raw moments / rho and their derivatives, blocks (1,4,5,7,14,16),
-    // (2,8,10,12), (3,9,11,13), (6,15)
-    const double mee[6] = {1.0, u2 + a * T, ux2 + T, uy2 + T, ux2 * A4 + T * A2, uy2 * A4 + T * A2};
-    const double moe[4] = {ux, ux * A2, ux * (ux2 + 3.0 * T), ux * (uy2 + T)};
-    const double meo[4] = {uy, uy * A2, uy * (ux2 + T), uy * (uy2 + 3.0 * T)};
-    const double moo[2] = {uxy, uxy * A4};
-    const double ee_x[6] = {0.0, 2.0 * ux, 2.0 * ux, 0.0, 2.0 * ux * (A4 + ux2 + T),
-                            2.0 * ux * (uy2 + T)};
-    const double ee_y[6] = {0.0, 2.0 * uy, 0.0, 2.0 * uy, 2.0 * uy * (ux2 + T),
-                            2.0 * uy * (A4 + uy2 + T)};
-    const double ee_T[6] = {0.0, a, 1.0, 1.0, ux2 * (a + 4.0) + A2 + T * (a + 2.0),
-                            uy2 * (a + 4.0) + A2 + T * (a + 2.0)};
-    const double oe_x[4] = {1.0, A2 + 2.0 * ux2, 3.0 * (ux2 + T), uy2 + T};
-    const double oe_y[4] = {0.0, 2.0 * uxy, 0.0, 2.0 * uxy};
-    const double oe_T[4] = {0.0, ux * (a + 2.0), 3.0 * ux, ux};
-    const double eo_x[4] = {0.0, 2.0 * uxy, 2.0 * uxy, 0.0};
-    const double eo_y[4] = {1.0, A2 + 2.0 * uy2, ux2 + T, 3.0 * (uy2 + T)};
-    const double eo_T[4] = {0.0, uy * (a + 2.0), uy, 3.0 * uy};
-    const double oo_x[2] = {uy, uy * (A4 + 2.0 * ux2)};
-    const double oo_y[2] = {ux, ux * (A4 + 2.0 * uy2)};
-    const double oo_T[2] = {0.0, uxy * (a + 4.0)};
     double gr = 0.0, gx = 0.0, gy = 0.0, gT = 0.0;
+    {
+        double wee[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        gr = fma(wee[c], mee[c], gr);
-        gx = fma(wee[c], ee_x[c], gx);
-        gy = fma(wee[c], ee_y[c], gy);
-        gT = fma(wee[c], ee_T[c], gT);
+        for (int c = 0; c < 6; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < 6; ++r) s = fma(K.iee[r][c], hb.ee[r], s);
+            wee[c] = s;
+        }
+        const double mee[6] = {1.0, u2 + a * T, ux2 + T, uy2 + T, ux2 * A4 + T * A2,
+                               uy2 * A4 + T * A2};
+        const double ee_x[6] = {0.0, 2.0 * ux, 2.0 * ux, 0.0, 2.0 * ux * (A4 + ux2 + T),
+                                2.0 * ux * (uy2 + T)};
+        const double ee_y[6] = {0.0, 2.0 * uy, 0.0, 2.0 * uy, 2.0 * uy * (ux2 + T),
+                                2.0 * uy * (A4 + uy2 + T)};
+        const double ee_T[6] = {0.0, a, 1.0, 1.0, ux2 * (a + 4.0) + A2 + T * (a + 2.0),
+                                uy2 * (a + 4.0) + A2 + T * (a + 2.0)};
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            gr = fma(wee[c], mee[c], gr);
+            gx = fma(wee[c], ee_x[c], gx);
+            gy = fma(wee[c], ee_y[c], gy);
+            gT = fma(wee[c], ee_T[c], gT);
+        }
     }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        double woe[4], weo[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        gr = fma(woe[c], moe[c], fma(weo[c], meo[c], gr));
-        gx = fma(woe[c], oe_x[c], fma(weo[c], eo_x[c], gx));
-        gy = fma(woe[c], oe_y[c], fma(weo[c], eo_y[c], gy));
-        gT = fma(woe[c], oe_T[c], fma(weo[c], eo_T[c], gT));
+        for (int c = 0; c < 4; ++c) {
+            double so = 0.0, se = 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                so = fma(K.ioe[r][c], hb.oe[r], so);
+                se = fma(K.ieo[r][c], hb.eo[r], se);
+            }
+            woe[c] = so;
+            weo[c] = se;
+        }
+        const double moe[4] = {ux, ux * A2, ux * (ux2 + 3.0 * T), ux * (uy2 + T)};
+        const double meo[4] = {uy, uy * A2, uy * (ux2 + T), uy * (uy2 + 3.0 * T)};
+        const double oe_x[4] = {1.0, A2 + 2.0 * ux2, 3.0 * (ux2 + T), uy2 + T};
+        const double oe_y[4] = {0.0, 2.0 * uxy, 0.0, 2.0 * uxy};
+        const double oe_T[4] = {0.0, ux * (a + 2.0), 3.0 * ux, ux};
+        const double eo_x[4] = {0.0, 2.0 * uxy, 2.0 * uxy, 0.0};
+        const double eo_y[4] = {1.0, A2 + 2.0 * uy2, ux2 + T, 3.0 * (uy2 + T)};
+        const double eo_T[4] = {0.0, uy * (a + 2.0), uy, 3.0 * uy};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            gr = fma(woe[c], moe[c], fma(weo[c], meo[c], gr));
+            gx = fma(woe[c], oe_x[c], fma(weo[c], eo_x[c], gx));
+            gy = fma(woe[c], oe_y[c], fma(weo[c], eo_y[c], gy));
+            gT = fma(woe[c], oe_T[c], fma(weo[c], eo_T[c], gT));
+        }
     }
+    __builtin_amdgcn_sched_barrier(0);
+    {
+        double woo[2];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        gr = fma(woo[c], moo[c], gr);
-        gx = fma(woo[c], oo_x[c], gx);
-        gy = fma(woo[c], oo_y[c], gy);
-        gT = fma(woo[c], oo_T[c], gT);
+        for (int c = 0; c < 2; ++c) woo[c] = fma(K.ioo[0][c], hb.oo[0], K.ioo[1][c] * hb.oo[1]);
+        const double moo[2] = {uxy, uxy * A4};
+        const double oo_x[2] = {uy, uy * (A4 + 2.0 * ux2)};
+        const double oo_y[2] = {ux, ux * (A4 + 2.0 * uy2)};
+        const double oo_T[2] = {0.0, uxy * (a + 4.0)};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            gr = fma(woo[c], moo[c], gr);
+            gx = fma(woo[c], oo_x[c], gx);
+            gy = fma(woo[c], oo_y[c], gy);
+            gT = fma(woo[c], oo_T[c], gT);
+        }
     }
     return Quad{gr, m.rho * gx, m.rho * gy, m.rho * gT};
 }
@@ -172,42 +182,29 @@ __device__ __forceinline__ double moments_vjp_k(const Macro& m, const KParams& K
     return g.rho + (g.ux * cx + g.uy * cy + g.T * (e - a * m.T) / a) / m.rho;
 }
 
-// The transposes run on a tile staged in LDS: one velocity's state and
-// adjoint on a block of ATX x ATY cells plus a halo of AH cells each side
-// (positions mapped through the boundary already: periodic images or
-// zero-gradient copies; the adjoint is zero at zero-gradient ghosts, where
-// no real cell exists).  Positions are local tile indices along one line;
-// the global index of a position only decides which gathers a
-// zero-gradient side skips.
-// 32 x 4 cells: at 256 x 256, 512 blocks (two per compute unit) whose
-// halo-to-cell ratio (38 x 10 tile positions for 128 cells) still lets the
-// gathers come from L2; 64 x 4 (one block per compute unit) and 32 x 8
-// measured 6 % and 1 % slower per adjoint step, 64 x 2 and 32 x 2 (more halo)
-// 7 % and 20 % slower.
-constexpr int ATX = 32, ATY = 4, AH = 3;
-// Velocity groups of a stage-adjoint block: each group of ATX x ATY threads
-// takes every AG-th velocity, so a block keeps AG waves per 64 cells busy.
-constexpr int AG = 2;
-static_assert(NV % AG == 0, "every group must run the same number of velocity steps");
-constexpr int ATW = ATX + 2 * AH, ATH = ATY + 2 * AH;
-
-template <typename S>
-struct TileLine {
-    const S* base;   // tile element of local position 0 on the line
-    int stride;
-    __device__ __forceinline__ S at(int l) const { return base[l * stride]; }
-};
-
-// Face selections precomputed per tile position: bit 0 alpha, bit 1 beta of
-// minmod(F(l+1) - F(l), F(l) - F(l-1)) along the line (Eq. (16) branch order).
-struct SelLine {
-    const unsigned char* base;
-    int stride;
+// The transposes read one velocity's state and adjoint along a line (x or y)
+// through the cell, at offsets -3 .. 3 for the state and -2 .. 2 for the
+// adjoint, held in registers.  Positions are offsets from the cell (local
+// position 0); the global index of a position only decides which gathers a
+// zero-gradient side skips.  Face selections: bit 0 alpha, bit 1 beta of
+// minmod(F(l+1) - F(l), F(l) - F(l-1)) along the line (Eq. (16) branch
+// order), at offsets -2 .. 2.  Offsets outside -2 .. 2 occur only in gathers
+// that a zero-gradient side skips; they are clamped to keep every index in
+// the arrays.
+__device__ __forceinline__ constexpr int line_slot(int l) {
+    return (l < -2 ? -2 : (l > 2 ? 2 : l)) + 2;
+}
+struct RegSel {
+    unsigned char c[5];
     __device__ __forceinline__ void at(int l, double& al, double& be) const {
-        const int c = base[l * stride];
-        al = (double)(c & 1);
-        be = (double)(c >> 1);
+        const int k = c[line_slot(l)];
+        al = (double)(k & 1);
+        be = (double)(k >> 1);
     }
+};
+struct RegLine {
+    double v[5];   // the adjoint, zero at zero-gradient ghosts
+    __device__ __forceinline__ double at(int l) const { return v[line_slot(l)]; }
 };
 
 template <typename S>
@@ -218,10 +215,10 @@ __device__ __forceinline__ unsigned char face_code(S fm, S f0, S fp) {
 }
 
 // Gather of the NND transpose at local position lp, global position gp
-// (see the header), with the selections read from a SelLine.
+// (see the header).
 template <bool POS>
-__device__ __forceinline__ double nnd_gather(const SelLine& Sl, const TileLine<double>& A, int lp,
-                                             int gp, int n, int bc) {
+__device__ __forceinline__ double nnd_gather(const RegSel& Sl, const RegLine& A, int lp, int gp,
+                                             int n, int bc) {
     double acc = 0.0;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
@@ -255,8 +252,8 @@ __device__ __forceinline__ double nnd_gather(const SelLine& Sl, const TileLine<d
 // Full NND transpose at the real cell of local position lc, global position
 // gc, with the ghost aliases of a zero-gradient side folded in.
 template <bool POS>
-__device__ __forceinline__ double nnd_transpose(const SelLine& Sl, const TileLine<double>& A,
-                                                int lc, int gc, int n, int bc) {
+__device__ __forceinline__ double nnd_transpose(const RegSel& Sl, const RegLine& A, int lc, int gc,
+                                                int n, int bc) {
     double acc = nnd_gather<POS>(Sl, A, lc, gc, n, bc);
     if (bc == CDBM_ZERO_GRADIENT) {
         if (gc == 0)

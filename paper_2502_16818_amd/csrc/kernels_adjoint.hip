@@ -12,72 +12,43 @@ namespace {
 // out = w_add * add + w_in * E'(g)^T a, and the per-block partial sums of
 // w_in * sum_i a_i dE_i/dtau = w_in * sum_i a_i dt (g_i - g_i^eq) / tau^2.
 // The state g is in the storage precision S; adjoint vectors are double.
-// A block handles ATX x ATY cells with AG groups of ATX x ATY threads.  The
-// pointwise part (macroscopic state, equilibrium transpose, tau term) runs
-// one thread per cell, split over two groups, and is shared through LDS.
-// The NND transposes then run one velocity per group at a time (group k
-// takes velocities k, k + AG, ...) on a tile of g_i and a_i with a 3-cell
-// halo staged in LDS, so that every value a gather needs is loaded from HBM
-// once per block instead of once per use, and the groups keep AG times as
-// many waves busy as cells alone would.
-template <typename S>
-__global__ void __launch_bounds__(ATX * ATY * AG) k_stage_adjoint(const S* __restrict__ g,
-                                                                  const double* __restrict__ a,
-                                                                  const double* __restrict__ add,
-                                                                  double* __restrict__ out,
-                                                                  double w_in, double w_add,
-                                                                  KParams K,
-                                                                  double* __restrict__ tau_part) {
-    constexpr int NC = ATX * ATY;               // cells per block
-    constexpr int TILE = ATW * ATH;
-    constexpr int PER = (TILE + NC - 1) / NC;   // tile elements per thread of a group
-    __shared__ S Ft[AG][TILE];
-    __shared__ double At[AG][TILE];
-    __shared__ unsigned char Sx[AG][TILE], Sy[AG][TILE];   // face selections along x and y
-    __shared__ double Mq[8][NC];                            // rho, u_x, u_y, T, then q
-    __shared__ double red[NC];
-    const int tid = threadIdx.x;
-    const int grp = __builtin_amdgcn_readfirstlane(tid / NC);   // uniform per wave
-    const int cid = tid % NC;
-    const int lx = cid % ATX, ly = cid / ATX;
-    const int x0 = blockIdx.x * ATX, y0 = blockIdx.y * ATY;
-    const int x = x0 + lx, y = y0 + ly;
-    const int nx = K.nx, ny = K.ny;
-    const int64_t cells = (int64_t)nx * ny;
-    const bool inside = x < nx && y < ny;
+// A block is 64 cells of one row (blocks numbered along the row, then row by
+// row) and four waves.  Waves 0 and 1 form the pointwise part: wave 0 the
+// macroscopic state and the tau term, wave 1 the equilibrium transpose,
+// shared through LDS.  Then wave w takes velocities w, w + 4, w + 8 and
+// w + 12 and reads each velocity's stencils, the state on offsets -3 .. 3
+// (for the face selections at -2 .. 2) and the adjoint on -2 .. 2, along x
+// and along y, straight from global memory: neighbouring lanes share cache
+// lines, and a block meets one barrier.  At 97 vector registers five waves
+// fit per SIMD, so a 256^2 grid's 1024 blocks are all resident at once.
+constexpr int ARX = 64, ARW = 4;
+static_assert(NV % ARW == 0, "every wave takes the same number of velocities");
 
-    // the tile elements this thread stages: source offset within a plane, or
-    // a zero-gradient ghost (adjoint 0 there)
-    int64_t src[PER];
-    bool ghost[PER];
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-        const int idx = cid + e * NC;
-        const int tx = idx % ATW, ty = idx / ATW;
-        const int gx = x0 - AH + tx, gy = y0 - AH + ty;
-        src[e] = (int64_t)wrap_or_clamp(gy, ny, K.bcy) * nx + wrap_or_clamp(gx, nx, K.bcx);
-        ghost[e] = (K.bcx != CDBM_PERIODIC && (gx < 0 || gx >= nx)) ||
-                   (K.bcy != CDBM_PERIODIC && (gy < 0 || gy >= ny));
-    }
-    // tile values of the group's next velocity, loaded while the current one is used
-    S fnext[PER];
-    double anext[PER];
-    auto fetch = [&](int i) {
-#pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            if (cid + e * NC < TILE) {
-                fnext[e] = g[i * cells + src[e]];
-                anext[e] = ghost[e] ? 0.0 : a[i * cells + src[e]];
-            }
-        }
-    };
-    // pointwise part: group 0 the state and the tau term, group 1 the
-    // equilibrium transpose, both from the parity transforms pg = P g and
-    // pa = P a (P P^T = k I per group, k = 2 axis, 4 diagonal).  With h the
-    // parity form of f^eq (f^eq = P^T h), a . (g - f^eq) = pa . (pg / k - h).
+template <typename S>
+__global__ void __launch_bounds__(ARX * ARW) k_stage_adjoint(const S* __restrict__ g,
+                                                             const double* __restrict__ a,
+                                                             const double* __restrict__ add,
+                                                             double* __restrict__ out,
+                                                             double w_in, double w_add,
+                                                             KParams K,
+                                                             double* __restrict__ tau_part) {
+    __shared__ double Mq[8][ARX];   // rho, u_x, u_y, T, then q
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nx = K.nx, ny = K.ny;
+    const int bxn = (nx + ARX - 1) / ARX;
+    const int x = (int)(blockIdx.x % bxn) * ARX + lane, y = (int)(blockIdx.x / bxn);
+    const int64_t cells = (int64_t)nx * ny;
+    const bool inside = x < nx;
     const int64_t c = (int64_t)y * nx + x;
+
+    // pointwise part, from the parity transforms pg = P g and pa = P a
+    // (P P^T = k I per group, k = 2 axis, 4 diagonal): with h the parity form
+    // of f^eq (f^eq = P^T h), a . (g - f^eq) = pa . (pg / k - h).  Each wave
+    // loads what it needs, so that wave 1 holds pg only until the moments
+    // (this keeps the kernel at 97 registers).
     double tpart = 0.0;
-    if (grp < 2 && inside) {
+    if (w == 0 && inside) {
         Parity pg, pa;
         {
             double v[NV];
@@ -92,101 +63,119 @@ __global__ void __launch_bounds__(ATX * ATY * AG) k_stage_adjoint(const S* __res
             to_parity(v, pa);
         }
         const Macro m = macro_from_parity(pg, K, K.inv_a);
-        if (grp == 0) {
-            Parity h;
-            equilibrium_parity(m, K, K.a, h);
-            double d = 0.0;
+        Parity h;
+        equilibrium_parity(m, K, K.a, h);
+        double d = 0.0;
 #pragma unroll
-            for (int r = 0; r < 6; ++r)
-                d = fma(pa.ee[r], fma((r == 2 || r == 5) ? 0.25 : 0.5, pg.ee[r], -h.ee[r]), d);
+        for (int r = 0; r < 6; ++r)
+            d = fma(pa.ee[r], fma((r == 2 || r == 5) ? 0.25 : 0.5, pg.ee[r], -h.ee[r]), d);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const double k = (r & 1) ? 0.25 : 0.5;
-                d = fma(pa.oe[r], fma(k, pg.oe[r], -h.oe[r]), d);
-                d = fma(pa.eo[r], fma(k, pg.eo[r], -h.eo[r]), d);
-            }
-#pragma unroll
-            for (int r = 0; r < 2; ++r) d = fma(pa.oo[r], fma(0.25, pg.oo[r], -h.oo[r]), d);
-            tpart = (K.dt / (K.tau * K.tau)) * d;
-            Mq[0][cid] = m.rho;
-            Mq[1][cid] = m.ux;
-            Mq[2][cid] = m.uy;
-            Mq[3][cid] = m.T;
-        } else {
-            const Quad q = equilibrium_vjp_q_parity(m, K, K.a, pa);
-            Mq[4][cid] = q.rho;
-            Mq[5][cid] = q.ux;
-            Mq[6][cid] = q.uy;
-            Mq[7][cid] = q.T;
+        for (int r = 0; r < 4; ++r) {
+            const double k = (r & 1) ? 0.25 : 0.5;
+            d = fma(pa.oe[r], fma(k, pg.oe[r], -h.oe[r]), d);
+            d = fma(pa.eo[r], fma(k, pg.eo[r], -h.eo[r]), d);
         }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) d = fma(pa.oo[r], fma(0.25, pg.oo[r], -h.oo[r]), d);
+        tpart = (K.dt / (K.tau * K.tau)) * d;
+        Mq[0][lane] = m.rho;
+        Mq[1][lane] = m.ux;
+        Mq[2][lane] = m.uy;
+        Mq[3][lane] = m.T;
+    } else if (w == 1 && inside) {
+        Macro m;
+        {
+            Parity pg;
+            double v[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v[i] = (double)g[i * cells + c];
+            to_parity(v, pg);
+            m = macro_from_parity(pg, K, K.inv_a);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        Parity pa;
+        {
+            double v[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v[i] = a[i * cells + c];
+            to_parity(v, pa);
+        }
+        const Quad q = equilibrium_vjp_q_parity(m, K, K.a, pa);
+        Mq[4][lane] = q.rho;
+        Mq[5][lane] = q.ux;
+        Mq[6][lane] = q.uy;
+        Mq[7][lane] = q.T;
     }
-    fetch(grp);
     __syncthreads();
-    Macro m{};
-    Quad q{};
-    if (inside) {
-        m = Macro{Mq[0][cid], Mq[1][cid], Mq[2][cid], Mq[3][cid]};
-        q = Quad{Mq[4][cid], Mq[5][cid], Mq[6][cid], Mq[7][cid]};
+    if (w == 0) {   // the block's tau partial, summed in a fixed order
+        double v = tpart * w_in;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) tau_part[blockIdx.x] = v;
     }
-    S* const F = Ft[grp];
-    double* const Ag = At[grp];
-    unsigned char* const Sxg = Sx[grp];
-    unsigned char* const Syg = Sy[grp];
-    const SelLine Srow{Sxg + (ly + AH) * ATW, 1}, Scol{Syg + lx + AH, ATW};
-    const TileLine<double> Arow{Ag + (ly + AH) * ATW, 1}, Acol{Ag + lx + AH, ATW};
-    // every group runs NV / AG iterations, so all threads meet every barrier
+    if (!inside) return;
+    const Macro m{Mq[0][lane], Mq[1][lane], Mq[2][lane], Mq[3][lane]};
+    const Quad q{Mq[4][lane], Mq[5][lane], Mq[6][lane], Mq[7][lane]};
+
+    // stencil positions, offsets -3 .. 3, through the boundary conditions;
+    // the adjoint is zero at zero-gradient ghosts
+    const int64_t row = (int64_t)y * nx;
+    int xs[7], ys[7];
+    bool xg[7], yg[7];
+#pragma unroll
+    for (int d = -3; d <= 3; ++d) {
+        xs[d + 3] = wrap_or_clamp(x + d, nx, K.bcx);
+        ys[d + 3] = wrap_or_clamp(y + d, ny, K.bcy);
+        xg[d + 3] = K.bcx != CDBM_PERIODIC && (x + d < 0 || x + d >= nx);
+        yg[d + 3] = K.bcy != CDBM_PERIODIC && (y + d < 0 || y + d >= ny);
+    }
 #pragma unroll 1
-    for (int i = grp; i < NV; i += AG) {
-        __syncthreads();   // the previous velocity's tiles are no longer read
+    for (int j = 0; j < NV / ARW; ++j) {
+        const int i = w + ARW * j;
+        const int sx = SX[i], sy = SY[i];
+        const S* gi = g + i * cells;
+        const double* ai = a + i * cells;
+        const S fc = gi[c];
+        const double ac = ai[c];
+        double adv = 0.0;
+        if (sx != 0) {
+            S F[7];
+            RegSel Sl;
+            RegLine A;
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = cid + e * NC;
-            if (idx < TILE) {
-                F[idx] = fnext[e];
-                Ag[idx] = anext[e];
-            }
-        }
-        if (i + AG < NV) fetch(i + AG);
-        __syncthreads();
-        const int sx = SX[i & (NV - 1)], sy = SY[i & (NV - 1)];
-        // selection of every tile position with both line neighbours in the tile
+            for (int d = 0; d < 7; ++d) F[d] = d == 3 ? fc : gi[row + xs[d]];
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-            const int idx = cid + e * NC;
-            if (idx < TILE) {
-                const int tx = idx % ATW, ty = idx / ATW;
-                if (sx != 0 && tx > 0 && tx < ATW - 1)
-                    Sxg[idx] = face_code<S>(F[idx - 1], F[idx], F[idx + 1]);
-                if (sy != 0 && ty > 0 && ty < ATH - 1)
-                    Syg[idx] = face_code<S>(F[idx - ATW], F[idx], F[idx + ATW]);
+            for (int d = 0; d < 5; ++d) {
+                Sl.c[d] = face_code<S>(F[d], F[d + 1], F[d + 2]);
+                A.v[d] = d == 2 ? ac : (xg[d + 1] ? 0.0 : ai[row + xs[d + 1]]);
             }
-        }
-        __syncthreads();
-        if (inside) {
-            const double ceq = moments_vjp_k(m, K, K.a, q, i);
-            double adv = 0.0;
             if (sx > 0)
-                adv += K.cx[i] * nnd_transpose<true>(Srow, Arow, lx + AH, x, nx, K.bcx);
-            else if (sx < 0)
-                adv += K.cx[i] * nnd_transpose<false>(Srow, Arow, lx + AH, x, nx, K.bcx);
-            if (sy > 0)
-                adv += K.cy[i] * nnd_transpose<true>(Scol, Acol, ly + AH, y, ny, K.bcy);
-            else if (sy < 0)
-                adv += K.cy[i] * nnd_transpose<false>(Scol, Acol, ly + AH, y, ny, K.bcy);
-            const double ai = Arow.at(lx + AH);   // a_i at the cell
-            double v = ai + adv - K.z * (ai - ceq);
-            v *= w_in;
-            if (w_add != 0.0) v = fma(w_add, add[i * cells + c], v);
-            out[i * cells + c] = v;
+                adv += K.cx[i] * nnd_transpose<true>(Sl, A, 0, x, nx, K.bcx);
+            else
+                adv += K.cx[i] * nnd_transpose<false>(Sl, A, 0, x, nx, K.bcx);
         }
+        if (sy != 0) {
+            S F[7];
+            RegSel Sl;
+            RegLine A;
+#pragma unroll
+            for (int d = 0; d < 7; ++d) F[d] = d == 3 ? fc : gi[(int64_t)ys[d] * nx + x];
+#pragma unroll
+            for (int d = 0; d < 5; ++d) {
+                Sl.c[d] = face_code<S>(F[d], F[d + 1], F[d + 2]);
+                A.v[d] = d == 2 ? ac : (yg[d + 1] ? 0.0 : ai[(int64_t)ys[d + 1] * nx + x]);
+            }
+            if (sy > 0)
+                adv += K.cy[i] * nnd_transpose<true>(Sl, A, 0, y, ny, K.bcy);
+            else
+                adv += K.cy[i] * nnd_transpose<false>(Sl, A, 0, y, ny, K.bcy);
+        }
+        const double ceq = moments_vjp_k(m, K, K.a, q, i);
+        double v = ac + adv - K.z * (ac - ceq);
+        v *= w_in;
+        if (w_add != 0.0) v = fma(w_add, add[i * cells + c], v);
+        out[i * cells + c] = v;
     }
-    if (grp == 0) red[cid] = tpart * w_in;
-    __syncthreads();
-    for (int s = NC / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-    }
-    if (tid == 0) tau_part[blockIdx.y * gridDim.x + blockIdx.x] = red[0];
 }
 
 // dst[0] += scale * sum_b part[b], summed in a fixed order by one block.
@@ -266,16 +255,16 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 }  // namespace
 
 int stage_adjoint_blocks(const KParams& K) {
-    return (int)(blocks_for(K.nx, ATX) * blocks_for(K.ny, ATY));
+    return (int)(blocks_for(K.nx, ARX) * (unsigned)K.ny);
 }
 
 template <typename S>
 hipError_t launch_stage_adjoint(const void* g, const void* a, const void* add, void* out,
                                 double* tau_part, double w_in, double w_add, const KParams& K,
                                 hipStream_t st) {
-    const dim3 grid(blocks_for(K.nx, ATX), blocks_for(K.ny, ATY));
-    hipLaunchKernelGGL(k_stage_adjoint<S>, grid, dim3(ATX * ATY * AG), 0, st, (const S*)g, (const double*)a,
-                       (const double*)add, (double*)out, w_in, w_add, K, tau_part);
+    hipLaunchKernelGGL(k_stage_adjoint<S>, dim3(stage_adjoint_blocks(K)), dim3(ARX * ARW), 0, st,
+                       (const S*)g, (const double*)a, (const double*)add, (double*)out, w_in,
+                       w_add, K, tau_part);
     return hipGetLastError();
 }
 
