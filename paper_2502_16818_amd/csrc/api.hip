@@ -248,8 +248,9 @@ int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
     h->cells = (int64_t)p->nx * p->ny;
     h->elem = mixed(h) ? sizeof(float) : sizeof(double);
     h->fbytes = (size_t)cdbm::NV * (size_t)h->cells * h->elem;
-    // tau partials of the two stage adjoints of a step, side by side
-    const int tau_blocks = 2 * stage_adjoint_blocks(h->k);
+    // tau partials of the two stage adjoints of a step, side by side, then
+    // room for the second-level sums of a two-pass accumulation
+    const int tau_blocks = 2 * stage_adjoint_blocks(h->k) + ACCUMULATE_BLOCKS;
     h->split = p->step_form == CDBM_STEP_SPLIT ||
                (p->step_form == CDBM_STEP_AUTO &&
                 h->cells <= (mixed(h) ? SPLIT_STEP_CELLS_MIXED : SPLIT_STEP_CELLS_FP64));

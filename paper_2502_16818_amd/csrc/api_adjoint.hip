@@ -40,7 +40,7 @@ int step_adjoint_impl(cdbm_handle* h, const void* f_n, const void* f1, const voi
     e = launch_stage_adjoint<S>(f_n, h->lam_mid, lam_np1, lam_n, h->tau_part + nb, 1.0, 0.5, K, st);
     if (e != hipSuccess) return hip_fail(e, "stage adjoint launch");
     // both stages' tau partials in one fixed-order sum
-    e = launch_accumulate_scalar(h->tau_part, 2 * nb, 1.0, dtau, st);
+    e = launch_accumulate_scalar(h->tau_part, 2 * nb, h->tau_part + 2 * nb, 1.0, dtau, st);
     if (e != hipSuccess) return hip_fail(e, "tau accumulation launch");
     return CDBM_OK;
 }

@@ -178,29 +178,49 @@ __global__ void __launch_bounds__(ARX * ARW) k_stage_adjoint(const S* __restrict
     }
 }
 
-// dst[0] += scale * sum_b part[b], summed in a fixed order by one block.
-__global__ void __launch_bounds__(256) k_accumulate(const double* __restrict__ part, int n,
-                                                    double scale, double* __restrict__ dst) {
-    __shared__ double red[256];
+// Sum of part[i], part[i + step], ... (i < n) over the 1024 threads of a
+// block, thread t starting at its own i, in a fixed order: up to four loads
+// in flight per thread, each wave's 64 sums by shuffles, then the 16 wave
+// sums by the first wave.  The result is valid in thread 0.
+__device__ __forceinline__ double block_sum_1024(const double* __restrict__ part, int64_t i,
+                                                 int64_t step, int64_t n) {
+    __shared__ double red[16];
     double s = 0.0;
-    int b = threadIdx.x;
-    // each thread's values in the order b, b + 256, ...; four loads in
-    // flight at a time instead of one
-    for (; b + 3 * 256 < n; b += 4 * 256) {
+    for (; i + 3 * step < n; i += 4 * step) {
         double v[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = part[b + k * 256];
+        for (int k = 0; k < 4; ++k) v[k] = part[i + k * step];
 #pragma unroll
         for (int k = 0; k < 4; ++k) s += v[k];
     }
-    for (; b < n; b += 256) s += part[b];
-    red[threadIdx.x] = s;
+    for (; i < n; i += step) s += part[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < 64) {
+        t = threadIdx.x < 16 ? red[threadIdx.x] : 0.0;
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o);
     }
-    if (threadIdx.x == 0) dst[0] += scale * red[0];
+    return t;
+}
+
+// dst[0] += scale * sum_b part[b] by one block.
+__global__ void __launch_bounds__(1024) k_accumulate(const double* __restrict__ part, int64_t n,
+                                                     double scale, double* __restrict__ dst) {
+    const double t = block_sum_1024(part, threadIdx.x, 1024, n);
+    if (threadIdx.x == 0) dst[0] += scale * t;
+}
+
+// out[k] = sum of part[b] over b = 1024 k + t + j 1024 gridDim.x: the first
+// pass of a two-pass sum of many partials.
+__global__ void __launch_bounds__(1024) k_partial_sum(const double* __restrict__ part, int64_t n,
+                                                      double* __restrict__ out) {
+    const double t = block_sum_1024(part, (int64_t)blockIdx.x * 1024 + threadIdx.x,
+                                    (int64_t)gridDim.x * 1024, n);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 // g_q = (d f^eq(q) / d q)^T lam per cell.
@@ -288,9 +308,15 @@ hipError_t launch_moments_adjoint(const void* f, const double* g_rho, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_accumulate_scalar(const double* part, int nblocks, double scale, double* dst,
-                                    hipStream_t st) {
-    hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(256), 0, st, part, nblocks, scale, dst);
+hipError_t launch_accumulate_scalar(const double* part, int n, double* scratch, double scale,
+                                    double* dst, hipStream_t st) {
+    if (n > ACCUMULATE_ONE_PASS) {
+        hipLaunchKernelGGL(k_partial_sum, dim3(ACCUMULATE_BLOCKS), dim3(1024), 0, st, part,
+                           (int64_t)n, scratch);
+        part = scratch;
+        n = ACCUMULATE_BLOCKS;
+    }
+    hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(1024), 0, st, part, (int64_t)n, scale, dst);
     return hipGetLastError();
 }
 

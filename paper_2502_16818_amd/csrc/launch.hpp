@@ -57,9 +57,12 @@ template <typename S>
 hipError_t launch_moments_adjoint(const void* f, const double* g_rho, const double* g_ux,
                                   const double* g_uy, const double* g_T, void* lam,
                                   const KParams& K, hipStream_t st);
-// dst[0] += scale * sum of part[0 .. nblocks), in a fixed order.
-hipError_t launch_accumulate_scalar(const double* part, int nblocks, double scale, double* dst,
-                                    hipStream_t st);
+// dst[0] += scale * sum of part[0 .. n), in a fixed order.  Above
+// ACCUMULATE_ONE_PASS partials a first pass writes ACCUMULATE_BLOCKS
+// second-level sums into scratch (unused otherwise).
+constexpr int ACCUMULATE_ONE_PASS = 8192, ACCUMULATE_BLOCKS = 256;
+hipError_t launch_accumulate_scalar(const double* part, int n, double* scratch, double scale,
+                                    double* dst, hipStream_t st);
 
 // Batched ensemble (kernels_batch.hip).  Ks: per-grid constants (device);
 // f_off: element offset of each grid's f block (device); work_start: prefix

@@ -58,6 +58,26 @@ def test_step_adjoint_fp64_matches_oracle(run):
     assert terr < 1e-10
 
 
+def test_step_adjoint_tall_grid_two_pass_tau_sum():
+    """A 64 x 4100 grid: 4100 row blocks per stage adjoint, 8200 tau partials
+    per step, more than one block sums in one pass, so dL/dtau goes through
+    the two-pass sum."""
+    run = W.random_periodic(64, 4100, seed=11, dt=1e-4, tau=2e-4)
+    run.bc_y = W.ZERO_GRADIENT
+    p, f0 = oracle_f0(run)
+    f = C.run(f0, p, 1)
+    lam = torch.from_numpy(np.random.default_rng(9).standard_normal(f.shape))
+    want_l, want_tau = C.step_vjp(f, lam, p)
+    s = _solver(run, FP64)
+    dtau = torch.full((1,), 3.0, dtype=torch.float64, device="cuda")
+    got_l, dtau = s.step_adjoint(_cuda(f), _cuda(lam), dtau=dtau)
+    err = rel_max(to_np(got_l), want_l.numpy())
+    terr = abs(float(dtau.item()) - 3.0 - want_tau) / abs(want_tau)
+    print(f"  lam rel err {err:.2e}, dtau rel err {terr:.2e}")
+    assert err < 1e-11
+    assert terr < 1e-10
+
+
 def test_step_adjoint_accumulates_tau():
     run = _cases()[0]
     p, f = _state(run)
