@@ -198,10 +198,14 @@ int cdbm_conserved_totals_static(const cdbm_params* p, const void* f, double* ou
  * device double [16][ny][nx] in both precision forms (adjoint vectors carry
  * gradients in small deviations between velocities that FP32 would round
  * away); lam_n must not overlap f_n or lam_np1.  dL_dtau: device double[1],
- * accumulated (never overwritten).  minmod passes the derivative to its first
- * argument on a tie |X| = |Y| and none when its value is 0 (the branch order
- * of Eq. (16)).  Uses the handle's scratch buffer, so calls on one handle
- * must be ordered on one stream. */
+ * accumulated (never overwritten); or NULL, and the step's dL/dtau term is
+ * added to the handle's accumulator instead, one double per block of the
+ * stage-adjoint launch, to be summed by cdbm_tau_collect (a reverse pass
+ * over many steps then pays for one sum instead of one per step; the total
+ * differs from per-step sums by rounding order only).  minmod passes the
+ * derivative to its first argument on a tie |X| = |Y| and none when its
+ * value is 0 (the branch order of Eq. (16)).  Uses the handle's scratch
+ * buffer, so calls on one handle must be ordered on one stream. */
 int cdbm_step_adjoint(cdbm_handle* h, const void* f_n, const void* lam_np1, void* lam_n,
                       double* dL_dtau, void* stream);
 
@@ -224,6 +228,13 @@ int cdbm_step_keep_stage(cdbm_handle* h, const void* f_in, void* f1_out, void* f
  * lam_n must not overlap f1 either.  Saves one single-stage launch. */
 int cdbm_step_adjoint_stage(cdbm_handle* h, const void* f_n, const void* f1,
                             const void* lam_np1, void* lam_n, double* dL_dtau, void* stream);
+
+/* *dL_dtau += the sum, in a fixed order, of the dL/dtau terms that step
+ * adjoints called with dL_dtau = NULL have added to the handle's accumulator
+ * since the handle was created or last collected; the accumulator is
+ * cleared (no step adjoint with NULL may run in between on another stream).
+ * dL_dtau: device double[1].  Two launches at most, no allocation. */
+int cdbm_tau_collect(cdbm_handle* h, double* dL_dtau, void* stream);
 
 /* Reverse-mode product of cdbm_init: g_q = (d f^eq(q) / d q)^T lam_f0 for
  * q = (rho, u_x, u_y, T) taken from the given fields (device double [ny][nx]).

@@ -25,7 +25,7 @@ EXPORTS = (
     "cdbm_last_error", "cdbm_create", "cdbm_destroy", "cdbm_get_params", "cdbm_init",
     "cdbm_step", "cdbm_moments", "cdbm_tne", "cdbm_tne_raw", "cdbm_conserved_totals",
     "cdbm_step_adjoint",
-    "cdbm_step_keep_stage", "cdbm_step_adjoint_stage",
+    "cdbm_step_keep_stage", "cdbm_step_adjoint_stage", "cdbm_tau_collect",
     "cdbm_init_adjoint", "cdbm_moments_adjoint", "cdbm_batch_create", "cdbm_batch_destroy",
     "cdbm_batch_init", "cdbm_batch_step", "cdbm_conserved_totals_static",
     "cdbm_batch_get_launch", "cdbm_batch_set_launch", "cdbm_batch_autotune",
@@ -90,6 +90,7 @@ def load() -> ctypes.CDLL:
         "cdbm_step_adjoint": ([_vp, _vp, _vp, _vp, _vp, _vp], _i32),
         "cdbm_step_keep_stage": ([_vp, _vp, _vp, _vp, _vp], _i32),
         "cdbm_step_adjoint_stage": ([_vp] * 7, _i32),
+        "cdbm_tau_collect": ([_vp, _vp, _vp], _i32),
         "cdbm_init_adjoint": ([_vp] * 11, _i32),
         "cdbm_moments_adjoint": ([_vp] * 8, _i32),
         "cdbm_batch_create": ([P, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_vp)], _i32),
@@ -259,21 +260,37 @@ class Solver:
     def step_adjoint(self, f_n: torch.Tensor, lam_np1: torch.Tensor,
                      lam_n: Optional[torch.Tensor] = None,
                      dtau: Optional[torch.Tensor] = None,
-                     f1: Optional[torch.Tensor] = None):
+                     f1: Optional[torch.Tensor] = None,
+                     defer_tau: bool = False):
         """Transpose of one step; f1, if given, is the step's first stage (as
-        step_keep_stage returns it) and saves its recomputation."""
+        step_keep_stage returns it) and saves its recomputation.  With
+        defer_tau the step's dL/dtau term goes to the handle's accumulator
+        (see tau_collect) and the returned dtau is None."""
         lam_n = self.empty_lam() if lam_n is None else lam_n
-        dtau = torch.zeros(1, dtype=torch.float64, device="cuda") if dtau is None else dtau
+        if defer_tau:
+            if dtau is not None:
+                raise ValueError("defer_tau takes no dtau")
+            dptr = None
+        else:
+            dtau = torch.zeros(1, dtype=torch.float64, device="cuda") if dtau is None else dtau
+            dptr = _ptr(dtau, torch.float64, 1)
         if f1 is None:
             _check(load().cdbm_step_adjoint(self._h, self._f(f_n), self._lam(lam_np1),
-                                            self._lam(lam_n), _ptr(dtau, torch.float64, 1),
-                                            _stream()), "cdbm_step_adjoint")
+                                            self._lam(lam_n), dptr, _stream()),
+                   "cdbm_step_adjoint")
         else:
             _check(load().cdbm_step_adjoint_stage(self._h, self._f(f_n), self._f(f1),
-                                                  self._lam(lam_np1), self._lam(lam_n),
-                                                  _ptr(dtau, torch.float64, 1), _stream()),
-                   "cdbm_step_adjoint_stage")
+                                                  self._lam(lam_np1), self._lam(lam_n), dptr,
+                                                  _stream()), "cdbm_step_adjoint_stage")
         return lam_n, dtau
+
+    def tau_collect(self, dtau: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """dtau += the dL/dtau terms of the step adjoints run with defer_tau
+        since the last collect; clears them."""
+        dtau = torch.zeros(1, dtype=torch.float64, device="cuda") if dtau is None else dtau
+        _check(load().cdbm_tau_collect(self._h, _ptr(dtau, torch.float64, 1), _stream()),
+               "cdbm_tau_collect")
+        return dtau
 
     def init_adjoint(self, rho, ux, uy, T, lam_f0: torch.Tensor):
         fs = [self._field(a) for a in (rho, ux, uy, T)]

@@ -259,15 +259,18 @@ int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
         ((h->split || h->two) && ensure_buffer(h, &h->stage) != CDBM_OK) ||
         hipMalloc(&h->partials, sizeof(double) * 4 * REDUCE_BLOCKS) != hipSuccess ||
         hipMalloc(&h->tau_part, sizeof(double) * tau_blocks) != hipSuccess ||
+        hipMalloc(&h->tau_acc, sizeof(double) * stage_adjoint_blocks(h->k)) != hipSuccess ||
         hipMalloc(&h->flag, sizeof(int)) != hipSuccess ||
         hipMalloc(&h->kdev, sizeof(KParams)) != hipSuccess) {
         cdbm_destroy(h);
         return fail(CDBM_ENOMEM, "device allocation failed");
     }
     e = hipMemcpy(h->kdev, &h->k, sizeof(KParams), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemset(h->tau_acc, 0, sizeof(double) * stage_adjoint_blocks(h->k));
     if (e != hipSuccess) {
         cdbm_destroy(h);
-        return hip_fail(e, "hipMemcpy of the run constants");
+        return hip_fail(e, "copying the run constants / clearing the tau accumulator");
     }
     *out = h;
     return CDBM_OK;
@@ -282,6 +285,7 @@ int cdbm_destroy(cdbm_handle* h) {
     if (h->lam_mid) (void)hipFree(h->lam_mid);
     if (h->partials) (void)hipFree(h->partials);
     if (h->tau_part) (void)hipFree(h->tau_part);
+    if (h->tau_acc) (void)hipFree(h->tau_acc);
     if (h->flag) (void)hipFree(h->flag);
     if (h->kdev) (void)hipFree(h->kdev);
     delete h;

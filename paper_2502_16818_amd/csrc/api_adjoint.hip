@@ -35,12 +35,18 @@ int step_adjoint_impl(cdbm_handle* h, const void* f_n, const void* f1, const voi
         if (e != hipSuccess) return hip_fail(e, "stage recompute launch");
         f1 = h->stage;
     }
-    e = launch_stage_adjoint<S>(f1, lam_np1, nullptr, h->lam_mid, h->tau_part, 0.5, 0.0, K, st);
+    // without dtau, both stages add their block partials to the handle's
+    // accumulator (cdbm_tau_collect sums it); else they write them side by
+    // side and one fixed-order sum adds them to dtau
+    const bool defer = dtau == nullptr;
+    double* part2 = defer ? h->tau_acc : h->tau_part;
+    double* part1 = defer ? h->tau_acc : h->tau_part + nb;
+    e = launch_stage_adjoint<S>(f1, lam_np1, nullptr, h->lam_mid, part2, defer, 0.5, 0.0, K, st);
     if (e != hipSuccess) return hip_fail(e, "stage adjoint launch");
-    e = launch_stage_adjoint<S>(f_n, h->lam_mid, lam_np1, lam_n, h->tau_part + nb, 1.0, 0.5, K, st);
+    e = launch_stage_adjoint<S>(f_n, h->lam_mid, lam_np1, lam_n, part1, defer, 1.0, 0.5, K, st);
     if (e != hipSuccess) return hip_fail(e, "stage adjoint launch");
-    // both stages' tau partials in one fixed-order sum
-    e = launch_accumulate_scalar(h->tau_part, 2 * nb, h->tau_part + 2 * nb, 1.0, dtau, st);
+    if (defer) return CDBM_OK;
+    e = launch_accumulate_scalar(h->tau_part, 2 * nb, h->tau_part + 2 * nb, 1.0, dtau, false, st);
     if (e != hipSuccess) return hip_fail(e, "tau accumulation launch");
     return CDBM_OK;
 }
@@ -79,15 +85,24 @@ extern "C" {
 
 int cdbm_step_adjoint(cdbm_handle* h, const void* f_n, const void* lam_np1, void* lam_n,
                       double* dL_dtau, void* stream) {
-    if (!h || !f_n || !lam_np1 || !lam_n || !dL_dtau) return fail(CDBM_EINVAL, "null argument");
+    if (!h || !f_n || !lam_np1 || !lam_n) return fail(CDBM_EINVAL, "null argument");
     return step_adjoint_entry(h, f_n, nullptr, lam_np1, lam_n, dL_dtau, stream);
 }
 
 int cdbm_step_adjoint_stage(cdbm_handle* h, const void* f_n, const void* f1,
                             const void* lam_np1, void* lam_n, double* dL_dtau, void* stream) {
-    if (!h || !f_n || !f1 || !lam_np1 || !lam_n || !dL_dtau)
-        return fail(CDBM_EINVAL, "null argument");
+    if (!h || !f_n || !f1 || !lam_np1 || !lam_n) return fail(CDBM_EINVAL, "null argument");
     return step_adjoint_entry(h, f_n, f1, lam_np1, lam_n, dL_dtau, stream);
+}
+
+int cdbm_tau_collect(cdbm_handle* h, double* dL_dtau, void* stream) {
+    if (!h || !dL_dtau) return fail(CDBM_EINVAL, "null argument");
+    int rc = check_device(h);
+    if (rc != CDBM_OK) return rc;
+    const int nb = stage_adjoint_blocks(h->k);
+    hipError_t e = launch_accumulate_scalar(h->tau_acc, nb, h->tau_part + 2 * nb, 1.0, dL_dtau,
+                                            true, (hipStream_t)stream);
+    return e == hipSuccess ? CDBM_OK : hip_fail(e, "tau collect launch");
 }
 
 int cdbm_init_adjoint(cdbm_handle* h, const double* rho, const double* ux, const double* uy,

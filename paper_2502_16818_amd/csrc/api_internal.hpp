@@ -59,6 +59,7 @@ struct cdbm_handle {
     void* lam_mid = nullptr;    // f-sized buffer for the adjoint's intermediate product
     double* partials = nullptr; // reduction partials
     double* tau_part = nullptr; // per-block partial sums of the adjoint's tau term (two stages)
+    double* tau_acc = nullptr;  // per-block tau terms of step adjoints called without dL_dtau
     cdbm::KParams* kdev = nullptr;   // device copy of k
     int* flag = nullptr;        // device flag of the field check
     cdbm::StepGraph graph;

@@ -10,7 +10,8 @@ namespace cdbm {
 namespace {
 
 // out = w_add * add + w_in * E'(g)^T a, and the per-block partial sums of
-// w_in * sum_i a_i dE_i/dtau = w_in * sum_i a_i dt (g_i - g_i^eq) / tau^2.
+// w_in * sum_i a_i dE_i/dtau = w_in * sum_i a_i dt (g_i - g_i^eq) / tau^2
+// written to tau_part (acc = 0) or added to it (acc = 1).
 // The state g is in the storage precision S; adjoint vectors are double.
 // A block is 64 cells of one row (blocks numbered along the row, then row by
 // row) and four waves.  Waves 0 and 1 form the pointwise part: wave 0 the
@@ -31,7 +32,8 @@ __global__ void __launch_bounds__(ARX * ARW) k_stage_adjoint(const S* __restrict
                                                              double* __restrict__ out,
                                                              double w_in, double w_add,
                                                              KParams K,
-                                                             double* __restrict__ tau_part) {
+                                                             double* __restrict__ tau_part,
+                                                             int acc) {
     __shared__ double Mq[8][ARX];   // rho, u_x, u_y, T, then q
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -111,7 +113,7 @@ __global__ void __launch_bounds__(ARX * ARW) k_stage_adjoint(const S* __restrict
         double v = tpart * w_in;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-        if (lane == 0) tau_part[blockIdx.x] = v;
+        if (lane == 0) tau_part[blockIdx.x] = acc ? tau_part[blockIdx.x] + v : v;
     }
     if (!inside) return;
     const Macro m{Mq[0][lane], Mq[1][lane], Mq[2][lane], Mq[3][lane]};
@@ -181,19 +183,27 @@ __global__ void __launch_bounds__(ARX * ARW) k_stage_adjoint(const S* __restrict
 // Sum of part[i], part[i + step], ... (i < n) over the 1024 threads of a
 // block, thread t starting at its own i, in a fixed order: up to four loads
 // in flight per thread, each wave's 64 sums by shuffles, then the 16 wave
-// sums by the first wave.  The result is valid in thread 0.
-__device__ __forceinline__ double block_sum_1024(const double* __restrict__ part, int64_t i,
-                                                 int64_t step, int64_t n) {
+// sums by the first wave.  The result is valid in thread 0.  With clear,
+// every element read is set to zero.
+__device__ __forceinline__ double block_sum_1024(double* __restrict__ part, int64_t i,
+                                                 int64_t step, int64_t n, bool clear) {
     __shared__ double red[16];
     double s = 0.0;
     for (; i + 3 * step < n; i += 4 * step) {
         double v[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) v[k] = part[i + k * step];
+        if (clear) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) part[i + k * step] = 0.0;
+        }
 #pragma unroll
         for (int k = 0; k < 4; ++k) s += v[k];
     }
-    for (; i < n; i += step) s += part[i];
+    for (; i < n; i += step) {
+        s += part[i];
+        if (clear) part[i] = 0.0;
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -207,19 +217,20 @@ __device__ __forceinline__ double block_sum_1024(const double* __restrict__ part
     return t;
 }
 
-// dst[0] += scale * sum_b part[b] by one block.
-__global__ void __launch_bounds__(1024) k_accumulate(const double* __restrict__ part, int64_t n,
-                                                     double scale, double* __restrict__ dst) {
-    const double t = block_sum_1024(part, threadIdx.x, 1024, n);
+// dst[0] += scale * sum_b part[b] by one block (part cleared with clear).
+__global__ void __launch_bounds__(1024) k_accumulate(double* __restrict__ part, int64_t n,
+                                                     double scale, double* __restrict__ dst,
+                                                     int clear) {
+    const double t = block_sum_1024(part, threadIdx.x, 1024, n, clear != 0);
     if (threadIdx.x == 0) dst[0] += scale * t;
 }
 
 // out[k] = sum of part[b] over b = 1024 k + t + j 1024 gridDim.x: the first
 // pass of a two-pass sum of many partials.
-__global__ void __launch_bounds__(1024) k_partial_sum(const double* __restrict__ part, int64_t n,
-                                                      double* __restrict__ out) {
+__global__ void __launch_bounds__(1024) k_partial_sum(double* __restrict__ part, int64_t n,
+                                                      double* __restrict__ out, int clear) {
     const double t = block_sum_1024(part, (int64_t)blockIdx.x * 1024 + threadIdx.x,
-                                    (int64_t)gridDim.x * 1024, n);
+                                    (int64_t)gridDim.x * 1024, n, clear != 0);
     if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
@@ -280,11 +291,11 @@ int stage_adjoint_blocks(const KParams& K) {
 
 template <typename S>
 hipError_t launch_stage_adjoint(const void* g, const void* a, const void* add, void* out,
-                                double* tau_part, double w_in, double w_add, const KParams& K,
-                                hipStream_t st) {
+                                double* tau_part, bool tau_add, double w_in, double w_add,
+                                const KParams& K, hipStream_t st) {
     hipLaunchKernelGGL(k_stage_adjoint<S>, dim3(stage_adjoint_blocks(K)), dim3(ARX * ARW), 0, st,
                        (const S*)g, (const double*)a, (const double*)add, (double*)out, w_in,
-                       w_add, K, tau_part);
+                       w_add, K, tau_part, tau_add ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -308,21 +319,23 @@ hipError_t launch_moments_adjoint(const void* f, const double* g_rho, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_accumulate_scalar(const double* part, int n, double* scratch, double scale,
-                                    double* dst, hipStream_t st) {
+hipError_t launch_accumulate_scalar(double* part, int n, double* scratch, double scale,
+                                    double* dst, bool clear, hipStream_t st) {
     if (n > ACCUMULATE_ONE_PASS) {
         hipLaunchKernelGGL(k_partial_sum, dim3(ACCUMULATE_BLOCKS), dim3(1024), 0, st, part,
-                           (int64_t)n, scratch);
+                           (int64_t)n, scratch, clear ? 1 : 0);
         part = scratch;
         n = ACCUMULATE_BLOCKS;
+        clear = false;
     }
-    hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(1024), 0, st, part, (int64_t)n, scale, dst);
+    hipLaunchKernelGGL(k_accumulate, dim3(1), dim3(1024), 0, st, part, (int64_t)n, scale, dst,
+                       clear ? 1 : 0);
     return hipGetLastError();
 }
 
 #define CDBM_INSTANTIATE(S)                                                                      \
     template hipError_t launch_stage_adjoint<S>(const void*, const void*, const void*, void*,   \
-                                                double*, double, double, const KParams&,        \
+                                                double*, bool, double, double, const KParams&,  \
                                                 hipStream_t);                                   \
     template hipError_t launch_init_adjoint<S>(const double*, const double*, const double*,     \
                                                const double*, const void*, double*, double*,    \

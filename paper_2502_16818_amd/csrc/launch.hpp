@@ -43,12 +43,13 @@ hipError_t launch_step2_fused(const void* fin, void* fout, const KParams& K, con
                               hipStream_t st);
 
 // Adjoint (kernels_adjoint.hip).  tau_part: one double per block
-// (stage_adjoint_blocks), the block sums of the launch's tau term.
+// (stage_adjoint_blocks), the block sums of the launch's tau term, written
+// or (tau_add) added to what it holds.
 int stage_adjoint_blocks(const KParams& K);
 template <typename S>
 hipError_t launch_stage_adjoint(const void* f, const void* lam, const void* lam_add, void* out,
-                                double* tau_part, double w_in, double w_add, const KParams& K,
-                                hipStream_t st);
+                                double* tau_part, bool tau_add, double w_in, double w_add,
+                                const KParams& K, hipStream_t st);
 template <typename S>
 hipError_t launch_init_adjoint(const double* rho, const double* ux, const double* uy,
                                const double* T, const void* lam, double* g_rho, double* g_ux,
@@ -57,12 +58,13 @@ template <typename S>
 hipError_t launch_moments_adjoint(const void* f, const double* g_rho, const double* g_ux,
                                   const double* g_uy, const double* g_T, void* lam,
                                   const KParams& K, hipStream_t st);
-// dst[0] += scale * sum of part[0 .. n), in a fixed order.  Above
-// ACCUMULATE_ONE_PASS partials a first pass writes ACCUMULATE_BLOCKS
-// second-level sums into scratch (unused otherwise).
+// dst[0] += scale * sum of part[0 .. n), in a fixed order; with clear,
+// part is set to zero as it is read.  Above ACCUMULATE_ONE_PASS partials a
+// first pass writes ACCUMULATE_BLOCKS second-level sums into scratch
+// (unused otherwise).
 constexpr int ACCUMULATE_ONE_PASS = 8192, ACCUMULATE_BLOCKS = 256;
-hipError_t launch_accumulate_scalar(const double* part, int n, double* scratch, double scale,
-                                    double* dst, hipStream_t st);
+hipError_t launch_accumulate_scalar(double* part, int n, double* scratch, double scale,
+                                    double* dst, bool clear, hipStream_t st);
 
 // Batched ensemble (kernels_batch.hip).  Ks: per-grid constants (device);
 // f_off: element offset of each grid's f block (device); work_start: prefix

@@ -4,8 +4,9 @@
 f0 = f^eq(rho0, u0, T0), advances nsteps steps and returns the final
 (rho, u_x, u_y, T).  Its backward pass uses only the library's reverse-mode
 entry points: the moments adjoint seeds dL/df at the final step, every step
-is transposed with cdbm_step_adjoint (which also accumulates dL/dtau), and
-the initial-equilibrium adjoint maps dL/df0 to the initial fields.  Forward
+is transposed with cdbm_step_adjoint (its dL/dtau terms stay in the handle's
+per-block accumulator until one cdbm_tau_collect at the end), and the
+initial-equilibrium adjoint maps dL/df0 to the initial fields.  Forward
 states are checkpointed every `every` steps; the backward pass recomputes
 the states of one segment at a time from its checkpoint, and, while a
 segment's first Runge-Kutta stages fit in KEEP_STAGE_BYTES, keeps them
@@ -69,6 +70,8 @@ class CDBMRollout(torch.autograd.Function):
         lam = s.moments_adjoint(ctx.f_final, *grads)
         lam_next = s.empty_lam()
         dtau = torch.zeros(1, dtype=torch.float64, device="cuda")
+        # drop any terms an interrupted reverse pass left in the accumulator
+        s.tau_collect(torch.zeros(1, dtype=torch.float64, device="cuda"))
         segs = _segments(ctx.nsteps, ctx.every)
         nmax = min(ctx.every, ctx.nsteps)
         states = [s.empty_f() for _ in range(nmax)]
@@ -85,8 +88,10 @@ class CDBMRollout(torch.autograd.Function):
                 for j in range(1, n):
                     s.step(states[j - 1], states[j], nsteps=1)
             for j in reversed(range(n)):
-                s.step_adjoint(states[j], lam, lam_next, dtau, f1=stages[j] if keep else None)
+                s.step_adjoint(states[j], lam, lam_next, f1=stages[j] if keep else None,
+                               defer_tau=True)
                 lam, lam_next = lam_next, lam
+        s.tau_collect(dtau)
         rho0, ux0, uy0, T0 = ctx.saved_tensors
         g0 = s.init_adjoint(rho0, ux0, uy0, T0, lam)
         gtau = dtau.reshape(()).to(ctx.tau_like.dtype).to(ctx.tau_like.device) \

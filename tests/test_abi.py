@@ -105,6 +105,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.cdbm_step(None, None, None, 1, None) == -1
     assert lib.cdbm_step_keep_stage(None, None, None, None, None) == -1
     assert lib.cdbm_step_adjoint_stage(None, None, None, None, None, None, None) == -1
+    assert lib.cdbm_tau_collect(None, None, None) == -1
     assert lib.cdbm_destroy(None) == 0
 
 

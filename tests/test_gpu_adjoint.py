@@ -78,6 +78,39 @@ def test_step_adjoint_tall_grid_two_pass_tau_sum():
     assert terr < 1e-10
 
 
+@pytest.mark.parametrize("precision", [FP64, MIXED])
+def test_deferred_tau_terms_sum_to_the_per_step_terms(precision):
+    """Step adjoints with dL_dtau = NULL leave their terms in the handle's
+    accumulator; cdbm_tau_collect adds their sum (in another order than the
+    per-step sums, so to rounding) and clears it: a second collect adds 0.
+    The adjoint vectors are the same bit for bit either way."""
+    run = _cases()[0]
+    p, f = _state(run)
+    s = _solver(run, precision)
+    dt = torch.float64 if precision == FP64 else torch.float32
+    rng = np.random.default_rng(12)
+    lams = [_cuda(rng.standard_normal(f.shape)) for _ in range(3)]
+    fs = [_cuda(f, dt)]
+    for _ in range(2):
+        fs.append(s.step(fs[-1], nsteps=1))
+    want = torch.zeros(1, dtype=torch.float64, device="cuda")
+    outs = []
+    for fk, lk in zip(fs, lams):
+        lo, _ = s.step_adjoint(fk, lk, dtau=want)
+        outs.append(lo)
+    for fk, lk, lo in zip(fs, lams, outs):
+        ld, none = s.step_adjoint(fk, lk, defer_tau=True)
+        assert none is None
+        assert torch.equal(ld, lo)
+    got = torch.full((1,), 2.0, dtype=torch.float64, device="cuda")
+    s.tau_collect(got)
+    d = abs(got.item() - 2.0 - want.item()) / abs(want.item())
+    print(f"  deferred dL/dtau {got.item() - 2.0:.17g} per-step {want.item():.17g} rel {d:.2e}")
+    assert d < 1e-13
+    again = s.tau_collect()
+    assert again.item() == 0.0
+
+
 def test_step_adjoint_accumulates_tau():
     run = _cases()[0]
     p, f = _state(run)
