@@ -30,7 +30,11 @@ def _cases():
     d = W.random_periodic(3, 2, seed=4, dt=1e-4, tau=1e-4)
     e = W.random_periodic(64, 9, seed=5, dt=1e-4, tau=1e-4, vset="tg")
     e.bc_y = W.ZERO_GRADIENT
-    return [a, b, c, d, e]
+    # rows of three 64-cell blocks, the last one partial: stencils that cross
+    # block boundaries, and a zero-gradient edge in a partial block
+    g = W.random_periodic(130, 7, seed=6, dt=1e-4, tau=1e-4)
+    g.bc_x = W.ZERO_GRADIENT
+    return [a, b, c, d, e, g]
 
 
 def _state(run, nsteps=2):
@@ -139,7 +143,7 @@ def test_init_and_moments_adjoint_fp64(run):
     assert rel_max(to_np(got_f), want_f.numpy()) < 1e-11
 
 
-@pytest.mark.parametrize("run", _cases()[:3], ids=lambda r: r.name)
+@pytest.mark.parametrize("run", _cases()[:3] + _cases()[5:], ids=lambda r: r.name)
 def test_step_adjoint_mixed_against_fp64_oracle(run):
     """The mixed form stores f in FP32 (lambda stays FP64); the oracle gets the
     same FP32-rounded state and differentiates in FP64, so the comparison sees
