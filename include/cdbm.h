@@ -217,7 +217,9 @@ int cdbm_step_adjoint(cdbm_handle* h, const void* f_n, const void* lam_np1, void
  * f_out: device [16][ny][nx] in the handle's precision, pairwise
  * non-overlapping.  f_out equals what cdbm_step gives for one step bit for
  * bit.  Meant for reverse passes that keep the stages of recomputed steps
- * (see cdbm_step_adjoint_stage). */
+ * (see cdbm_step_adjoint_stage).  It writes no buffer of the handle, so it
+ * may run on another stream at the same time as the handle's step adjoints
+ * (on buffers they do not read). */
 int cdbm_step_keep_stage(cdbm_handle* h, const void* f_in, void* f1_out, void* f_out,
                          void* stream);
 

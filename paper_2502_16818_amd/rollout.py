@@ -11,7 +11,10 @@ states are checkpointed every `every` steps; the backward pass recomputes
 the states of one segment at a time from its checkpoint, and, while a
 segment's first Runge-Kutta stages fit in KEEP_STAGE_BYTES, keeps them
 (cdbm_step_keep_stage) so that the step adjoints need not recompute them
-(cdbm_step_adjoint_stage; the gradients are the same bit for bit).
+(cdbm_step_adjoint_stage; the gradients are the same bit for bit).  With
+kept stages, two buffer sets let the next segment's recompute run on a
+second stream while the current segment's step adjoints run (the two kinds
+of launch are short on small grids and leave the GPU idle on their own).
 """
 from __future__ import annotations
 
@@ -22,8 +25,9 @@ import torch
 
 from .cdbm import MIXED, Solver
 
-# Device memory the backward pass may spend on the first stages of one
-# segment's recomputed steps (one f per step).
+# Kept stages are used while one segment's first stages (one f per step)
+# take at most this much device memory; the backward pass then holds the
+# states and stages of two segments, four times that at most.
 KEEP_STAGE_BYTES = 8 << 30
 
 
@@ -72,31 +76,67 @@ class CDBMRollout(torch.autograd.Function):
         dtau = torch.zeros(1, dtype=torch.float64, device="cuda")
         # drop any terms an interrupted reverse pass left in the accumulator
         s.tau_collect(torch.zeros(1, dtype=torch.float64, device="cuda"))
-        segs = _segments(ctx.nsteps, ctx.every)
+        segs = list(zip(reversed(_segments(ctx.nsteps, ctx.every)), reversed(ctx.ckpts)))
         nmax = min(ctx.every, ctx.nsteps)
-        states = [s.empty_f() for _ in range(nmax)]
-        fbytes = states[0].numel() * states[0].element_size()
-        keep = nmax * fbytes <= KEEP_STAGE_BYTES
-        stages = [s.empty_f() for _ in range(nmax)] if keep else None
-        spare = s.empty_f() if keep else None   # state after a segment's last step, unused
-        for (k0, n), ck in zip(reversed(segs), reversed(ctx.ckpts)):
-            states[0].copy_(ck)
-            if keep:
-                for j in range(n):
-                    s.step_keep_stage(states[j], stages[j], states[j + 1] if j + 1 < n else spare)
-            else:
+        fbytes = ctx.f_final.numel() * ctx.f_final.element_size()
+        if nmax * fbytes <= KEEP_STAGE_BYTES:
+            lam = _reverse_kept(s, segs, nmax, lam, lam_next)
+        else:
+            states = [s.empty_f() for _ in range(nmax)]
+            for (_, n), ck in segs:
+                states[0].copy_(ck)
                 for j in range(1, n):
                     s.step(states[j - 1], states[j], nsteps=1)
-            for j in reversed(range(n)):
-                s.step_adjoint(states[j], lam, lam_next, f1=stages[j] if keep else None,
-                               defer_tau=True)
-                lam, lam_next = lam_next, lam
+                for j in reversed(range(n)):
+                    s.step_adjoint(states[j], lam, lam_next, defer_tau=True)
+                    lam, lam_next = lam_next, lam
         s.tau_collect(dtau)
         rho0, ux0, uy0, T0 = ctx.saved_tensors
         g0 = s.init_adjoint(rho0, ux0, uy0, T0, lam)
         gtau = dtau.reshape(()).to(ctx.tau_like.dtype).to(ctx.tau_like.device) \
             if ctx.needs_input_grad[4] else None
         return (*g0, gtau, None, None, None)
+
+
+def _reverse_kept(s: Solver, segs, nmax: int, lam, lam_next):
+    """Step adjoints of every segment (last first) with kept stages; returns
+    dL/df0.  A segment's states and first stages are recomputed on a side
+    stream into one of two buffer sets while the current stream transposes
+    the segment before it; events order each set's reuse.  The kernels and
+    their inputs are those of a one-stream pass, so the results are too."""
+    main = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    side.wait_stream(main)   # checkpoints and buffers were written on main
+    sets = [([s.empty_f() for _ in range(nmax)], [s.empty_f() for _ in range(nmax)],
+             s.empty_f()) for _ in range(2)]
+    ready = [torch.cuda.Event(), torch.cuda.Event()]
+    free = [None, None]
+
+    def recompute(k):
+        (_, n), ck = segs[k]
+        states, stages, spare = sets[k % 2]
+        with torch.cuda.stream(side):
+            if free[k % 2] is not None:
+                side.wait_event(free[k % 2])
+            states[0].copy_(ck)
+            for j in range(n):
+                s.step_keep_stage(states[j], stages[j], states[j + 1] if j + 1 < n else spare)
+            ready[k % 2].record(side)
+
+    recompute(0)
+    for k in range(len(segs)):
+        if k + 1 < len(segs):
+            recompute(k + 1)
+        (_, n), _ = segs[k]
+        states, stages, _ = sets[k % 2]
+        main.wait_event(ready[k % 2])
+        for j in reversed(range(n)):
+            s.step_adjoint(states[j], lam, lam_next, f1=stages[j], defer_tau=True)
+            lam, lam_next = lam_next, lam
+        done = torch.cuda.Event()
+        done.record(main)
+        free[k % 2] = done
+    return lam
 
 
 def rollout(solver: Solver, rho0, ux0, uy0, T0, tau, nsteps: int, every: int = 100):
