@@ -320,11 +320,12 @@ def field_errors(got, want):
 
 
 def headline_accuracy(run):
-    """The headline workload run for its full length in both forms; per-field
-    error of the mixed form against the FP64 one."""
-    from paper_2502_16818_amd import FP64, MIXED, Solver
+    """The headline workload run for its full length in the three forms;
+    per-field errors of the mixed and the compensated mixed form against the
+    FP64 one."""
+    from paper_2502_16818_amd import FP64, MIXED, MIXED_COMP, Solver
     fields = {}
-    for prec in (MIXED, FP64):
+    for prec in (MIXED, MIXED_COMP, FP64):
         s = Solver.from_run(run, prec)
         f = s.init(run.rho, run.ux, run.uy, run.T)
         g = s.step(f, nsteps=run.steps)
@@ -334,6 +335,7 @@ def headline_accuracy(run):
         s.close()
     res = field_errors(fields[MIXED], fields[FP64])
     res["steps"] = run.steps
+    res["compensated"] = field_errors(fields[MIXED_COMP], fields[FP64])
     return res
 
 
@@ -377,14 +379,14 @@ SOD_SHOCK_SPEED = 1.752156
 def tube_and_vortex_runs():
     """The paper-shaped runs beside the headline: the 500 x 1 Sod tube (FP64,
     5000 steps to t = 0.1), the 512 x 512 Taylor-Green vortex (10000 steps
-    to t = 1, FP64 and mixed) and the Sec. 3.4 sound wave's Mach cone (both
-    forms).  Reports time per step, the Sod shock position against the exact
+    to t = 1, FP64, mixed and compensated mixed) and the Sec. 3.4 sound
+    wave's Mach cone (FP64 and mixed).  Reports time per step, the Sod shock position against the exact
     one, the vortex's kinetic-energy decay against exp(-4 nu t), nu = T tau,
     and the cone's sin(theta) against 1/2."""
     import numpy as np
     import torch
     import workloads as W
-    from paper_2502_16818_amd import FP64, MIXED, Solver
+    from paper_2502_16818_amd import FP64, MIXED, MIXED_COMP, Solver
     out = {}
     run = W.sod_tube()
     s = Solver.from_run(run, FP64)
@@ -408,7 +410,7 @@ def tube_and_vortex_runs():
 
     tg = {}
     finals = {}
-    for prec, name in ((FP64, "fp64"), (MIXED, "mixed")):
+    for prec, name in ((FP64, "fp64"), (MIXED, "mixed"), (MIXED_COMP, "mixed_compensated")):
         run = W.taylor_green_2pi()
         s = Solver.from_run(run, prec)
         f = s.init(run.rho, run.ux, run.uy, run.T)
@@ -427,8 +429,9 @@ def tube_and_vortex_runs():
                     "ke_ratio_viscous": float(np.exp(-4 * nu * run.dt * run.steps))}
         finals[name] = ux1.clone()
         s.close()
-    diff = (finals["mixed"] - finals["fp64"]).norm() / finals["fp64"].norm()
-    tg["mixed_vs_fp64_ux_rel_l2"] = float(diff)
+    for name in ("mixed", "mixed_compensated"):
+        diff = (finals[name] - finals["fp64"]).norm() / finals["fp64"].norm()
+        tg[f"{name}_vs_fp64_ux_rel_l2"] = float(diff)
     tg["steps"] = W.taylor_green_2pi().steps
     out["taylor_green_512"] = tg
     out["sound_wave_1600x1200"] = {"fp64": sound_wave_run(FP64), "mixed": sound_wave_run(MIXED),
@@ -489,10 +492,13 @@ def main():
         sys.exit(2)
     import torch
     import workloads as W
-    from paper_2502_16818_amd import FP64, MIXED, Solver
+    from paper_2502_16818_amd import FP64, MIXED, MIXED_COMP, Solver
 
     run = W.headline(seed=args.seed, n=args.n)
     out = {}
+
+    def done(what):
+        print(f"bench: {what} done", file=sys.stderr, flush=True)
     if args.calibrate_copy:
         a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         c = torch.empty_like(a)
@@ -544,6 +550,7 @@ def main():
     copy_gbs = copy_bandwidth(torch)
     out["roofline"]["copy_GBs"] = copy_gbs
     out["roofline"]["frac_of_copy"] = achieved / copy_gbs
+    done("mixed headline")
 
     if not args.no_fp64:
         s = Solver.from_run(run, FP64)
@@ -557,6 +564,22 @@ def main():
         out["speedup_mixed_over_fp64"] = t64 / t_mixed
         del fa, fb
         s.close()
+        done("fp64")
+
+    if not args.no_fp64:
+        # compensated mixed form: FP32 f, FP64 arithmetic, conserved-moment
+        # residual (two single-stage launches; 20 floats per cell)
+        s = Solver.from_run(run, MIXED_COMP)
+        fa = s.init(run.rho, run.ux, run.uy, run.T)
+        fb = s.empty_f()
+        nst = max(args.steps // 4, 10)
+        tc, _ = time_steps(s, fa, fb, nst, args.warmup)
+        out["compensated"] = {"value": 16 * run.cells / tc, "ms_per_step": tc * 1e3, "steps": nst,
+                              "form": "two single-stage launches",
+                              "speedup_over_fp64": out["fp64"]["ms_per_step"] / (tc * 1e3)}
+        del fa, fb
+        s.close()
+        done("compensated")
 
     if not args.no_two_step:
         # temporal blocking: two steps per launch (f crosses HBM once per two steps)
@@ -574,12 +597,15 @@ def main():
             "note": "effective_roofline_frac prices the updates at the one-step 8 B each"}
         del fa, fb
         s.close()
+        done("two-step")
 
     if not args.no_batch:
         out["batched"] = batched_ensemble(args.batch_steps, args.warmup)
+        done("batched")
 
     if not args.no_paper_runs:
         out["paper_runs"] = tube_and_vortex_runs()
+        done("paper runs")
 
     if not args.no_adjoint:
         from paper_2502_16818_amd import FP64 as F64
@@ -593,16 +619,19 @@ def main():
                                                                       ref.pop("grads"))}
             adj["fp64_ratio"] = ref["ratio"]
         out["adjoint"] = adj
+        done("adjoint")
 
     if not args.no_accuracy:
         out["accuracy"] = {
-            "what": "relative L2 of the mixed form against the FP64 form of this library at the "
+            "what": "relative L2 of the mixed form (headline.compensated: of the compensated "
+                    "mixed form) against the FP64 form of this library at the "
                     "workloads' full run lengths (rho and T against their RMS, u against max|u|); "
                     "the FP64 form itself matches the CPU oracle to 1e-12",
             "headline": headline_accuracy(run),
         }
         if not args.no_batch:
             out["accuracy"]["batched"] = batched_accuracy()
+        done("accuracy")
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(run, args.cpu_sample, args.cpu_steps)

@@ -21,6 +21,10 @@
  *   v_a(0,-1); v_b(1,1), v_b(-1,1), v_b(-1,-1), v_b(1,-1); then groups c
  *   (axis) and d (diagonal) in the same order (Eq. (2)); eta_i per group
  *   (Eq. (3)).  Element type: double for CDBM_FP64, float for CDBM_MIXED.
+ *   A state of CDBM_MIXED_COMP is float [20][ny][nx]: the 16 planes of f,
+ *   then four planes r = (r_rho, r_jx, r_jy, r_2E) that carry what FP32
+ *   storage rounded off the cell's conserved moments (see `precision`);
+ *   every "[16][ny][nx]" of a state below reads "[20][ny][nx]" for it.
  * - Macroscopic fields are double arrays [y][x].
  * - Every pointer argument named as device memory must point to memory of
  *   the GPU that is current when the call is made.  The caller owns all
@@ -53,7 +57,7 @@ enum {
 };
 
 enum { CDBM_PERIODIC = 0, CDBM_ZERO_GRADIENT = 1 };
-enum { CDBM_FP64 = 0, CDBM_MIXED = 1 };
+enum { CDBM_FP64 = 0, CDBM_MIXED = 1, CDBM_MIXED_COMP = 2 };
 enum { CDBM_STEP_AUTO = 0, CDBM_STEP_FUSED = 1, CDBM_STEP_SPLIT = 2, CDBM_STEP_FUSED2 = 3 };
 
 /* Run parameters (Secs. 2 and 3).
@@ -74,6 +78,24 @@ enum { CDBM_STEP_AUTO = 0, CDBM_STEP_FUSED = 1, CDBM_STEP_SPLIT = 2, CDBM_STEP_F
  *   precision   CDBM_FP64: f stored and advected in double.  CDBM_MIXED: f
  *               stored and advected in float; moments, equilibrium and the
  *               relaxation difference f - f^eq in double.
+ *               CDBM_MIXED_COMP: f stored in float as in CDBM_MIXED, each
+ *               stage's arithmetic in double as in CDBM_FP64, and a
+ *               compensation of the conserved moments: each cell also
+ *               stores, in float, the
+ *               part r of its mass, momentum and energy that rounding f to
+ *               float removed: the cell's conserved moments are
+ *               sum_i f_i psi_i + r (psi = 1, v_x, v_y, |v|^2 + eta^2), in
+ *               the equilibrium, in cdbm_moments and in the totals.  A stage
+ *               forms each new f_i in double, rounds it to float, and adds
+ *               the conserved moments of what was rounded off to r; the
+ *               relaxation towards f^eq of those moments moves r back into
+ *               f (by dt/tau of it per stage).  Changes of the conserved
+ *               moments far below an FP32 unit of f per step (the viscous
+ *               decay of a nearly steady flow) accumulate instead of
+ *               rounding away.  Runs as two single-stage launches (step_form
+ *               CDBM_STEP_AUTO or CDBM_STEP_SPLIT); 20 floats per cell.  The
+ *               adjoint, keep-stage and batch entry points reject it
+ *               (EINVAL).
  *   step_form   how cdbm_step runs a time step; all forms give the same
  *               result up to rounding order.  CDBM_STEP_FUSED: both stages
  *               in one launch that streams strips of the grid through LDS

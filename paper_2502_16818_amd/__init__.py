@@ -6,6 +6,7 @@ This package holds the build script, the ctypes binding and the autograd
 wrapper of the hand-written adjoint.
 """
 from .cdbm import (  # noqa: F401
-    BATCH_CONTIGUOUS, BATCH_ROW_PIECES, EXPORTS, FP64, MIXED, PERIODIC, ZERO_GRADIENT, Batch,
+    BATCH_CONTIGUOUS, BATCH_ROW_PIECES, EXPORTS, FP64, MIXED, MIXED_COMP, PERIODIC, ZERO_GRADIENT,
+    Batch,
     CdbmError, Params, Solver, load, make_params,
 )

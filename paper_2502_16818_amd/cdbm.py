@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcdbm.so")
 
 OK, EINVAL, ESINGULAR, ENONPHYS, EHIP, ENOMEM = 0, -1, -2, -3, -4, -5
 PERIODIC, ZERO_GRADIENT = 0, 1
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_COMP = 0, 1, 2
 STEP_AUTO, STEP_FUSED, STEP_SPLIT, STEP_FUSED2 = 0, 1, 2, 3
 
 EXPORTS = (
@@ -170,7 +170,9 @@ class Solver:
         self._h = h
         self.params = params
         self.nx, self.ny = params.nx, params.ny
-        self.dtype = torch.float32 if params.precision == MIXED else torch.float64
+        self.dtype = torch.float32 if params.precision in (MIXED, MIXED_COMP) else torch.float64
+        # a compensated state carries four residual planes after the 16 of f
+        self.planes = 20 if params.precision == MIXED_COMP else 16
 
     @classmethod
     def from_run(cls, run, precision=FP64, step_form=0) -> "Solver":
@@ -190,13 +192,13 @@ class Solver:
 
     # -- buffers -----------------------------------------------------------
     def empty_f(self) -> torch.Tensor:
-        return torch.empty((16, self.ny, self.nx), dtype=self.dtype, device="cuda")
+        return torch.empty((self.planes, self.ny, self.nx), dtype=self.dtype, device="cuda")
 
     def empty_field(self, *lead) -> torch.Tensor:
         return torch.empty(tuple(lead) + (self.ny, self.nx), dtype=torch.float64, device="cuda")
 
     def _f(self, t: torch.Tensor) -> int:
-        return _ptr(t, self.dtype, 16 * self.nx * self.ny)
+        return _ptr(t, self.dtype, self.planes * self.nx * self.ny)
 
     def _lam(self, t: torch.Tensor) -> int:
         return _ptr(t, torch.float64, 16 * self.nx * self.ny)

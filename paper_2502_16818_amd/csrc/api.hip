@@ -193,6 +193,11 @@ constexpr int64_t SPLIT_STEP_CELLS_MIXED = int64_t(1) << 19;   // 724 x 724
 constexpr int64_t SPLIT_STEP_CELLS_FP64 = int64_t(1) << 18;    // 512 x 512
 
 hipError_t step_once(const cdbm_handle* h, const void* fin, void* fout, hipStream_t st) {
+    if (comp(h)) {
+        hipError_t e = launch_stage_comp(fin, nullptr, h->stage, false, h->k, h->kdev, st);
+        if (e != hipSuccess) return e;
+        return launch_stage_comp(h->stage, fin, fout, true, h->k, h->kdev, st);
+    }
     if (h->split) {
         hipError_t e = mixed(h) ? launch_stage<float>(fin, nullptr, h->stage, false, h->k, h->kdev, st)
                                 : launch_stage<double>(fin, nullptr, h->stage, false, h->k, h->kdev, st);
@@ -246,12 +251,12 @@ int cdbm_create(const cdbm_params* p, cdbm_handle** out) {
         return hip_fail(e, "hipGetDevice");
     }
     h->cells = (int64_t)p->nx * p->ny;
-    h->elem = mixed(h) ? sizeof(float) : sizeof(double);
-    h->fbytes = (size_t)cdbm::NV * (size_t)h->cells * h->elem;
+    h->elem = (mixed(h) || comp(h)) ? sizeof(float) : sizeof(double);
+    h->fbytes = (size_t)state_planes(p->precision) * (size_t)h->cells * h->elem;
     // tau partials of the two stage adjoints of a step, side by side, then
     // room for the second-level sums of a two-pass accumulation
     const int tau_blocks = 2 * stage_adjoint_blocks(h->k) + ACCUMULATE_BLOCKS;
-    h->split = p->step_form == CDBM_STEP_SPLIT ||
+    h->split = p->step_form == CDBM_STEP_SPLIT || comp(h) ||
                (p->step_form == CDBM_STEP_AUTO &&
                 h->cells <= (mixed(h) ? SPLIT_STEP_CELLS_MIXED : SPLIT_STEP_CELLS_FP64));
     h->two = p->step_form == CDBM_STEP_FUSED2;
@@ -306,8 +311,9 @@ int cdbm_init(cdbm_handle* h, const double* rho, const double* ux, const double*
     hipStream_t st = (hipStream_t)stream;
     rc = check_fields(h, rho, ux, uy, T, st);
     if (rc != CDBM_OK) return rc;
-    hipError_t e = mixed(h) ? cdbm::launch_init<float>(rho, ux, uy, T, f_out, h->k, st)
-                            : cdbm::launch_init<double>(rho, ux, uy, T, f_out, h->k, st);
+    hipError_t e = comp(h)    ? cdbm::launch_init_comp(rho, ux, uy, T, f_out, h->k, st)
+                   : mixed(h) ? cdbm::launch_init<float>(rho, ux, uy, T, f_out, h->k, st)
+                              : cdbm::launch_init<double>(rho, ux, uy, T, f_out, h->k, st);
     return e == hipSuccess ? CDBM_OK : hip_fail(e, "init launch");
 }
 
@@ -344,6 +350,7 @@ int cdbm_step(cdbm_handle* h, const void* f_in, void* f_out, int32_t nsteps, voi
 int cdbm_step_keep_stage(cdbm_handle* h, const void* f_in, void* f1_out, void* f_out,
                          void* stream) {
     if (!h || !f_in || !f1_out || !f_out) return fail(CDBM_EINVAL, "null argument");
+    if (comp(h)) return fail(CDBM_EINVAL, "cdbm_step_keep_stage does not take CDBM_MIXED_COMP");
     const char* a = (const char*)f_in;
     const char* b = (const char*)f1_out;
     const char* c = (const char*)f_out;
@@ -367,8 +374,9 @@ int cdbm_moments(cdbm_handle* h, const void* f, double* rho, double* ux, double*
     int rc = check_device(h);
     if (rc != CDBM_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = mixed(h) ? cdbm::launch_moments<float>(f, rho, ux, uy, T, h->k, st)
-                            : cdbm::launch_moments<double>(f, rho, ux, uy, T, h->k, st);
+    hipError_t e = comp(h)    ? cdbm::launch_moments_comp(f, rho, ux, uy, T, h->k, st)
+                   : mixed(h) ? cdbm::launch_moments<float>(f, rho, ux, uy, T, h->k, st)
+                              : cdbm::launch_moments<double>(f, rho, ux, uy, T, h->k, st);
     return e == hipSuccess ? CDBM_OK : hip_fail(e, "moments launch");
 }
 
@@ -378,8 +386,9 @@ int tne_common(cdbm_handle* h, const void* f, double* out12, bool raw, void* str
     int rc = check_device(h);
     if (rc != CDBM_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = mixed(h) ? cdbm::launch_tne<float>(f, out12, raw, h->k, st)
-                            : cdbm::launch_tne<double>(f, out12, raw, h->k, st);
+    hipError_t e = comp(h)    ? cdbm::launch_tne_comp(f, out12, raw, h->k, st)
+                   : mixed(h) ? cdbm::launch_tne<float>(f, out12, raw, h->k, st)
+                              : cdbm::launch_tne<double>(f, out12, raw, h->k, st);
     return e == hipSuccess ? CDBM_OK : hip_fail(e, "tne launch");
 }
 }  // namespace
@@ -397,9 +406,10 @@ int cdbm_conserved_totals(cdbm_handle* h, const void* f, double* out4, void* str
     int rc = check_device(h);
     if (rc != CDBM_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = mixed(h)
-                       ? cdbm::launch_totals<float>(f, h->partials, REDUCE_BLOCKS, out4, h->k, st)
-                       : cdbm::launch_totals<double>(f, h->partials, REDUCE_BLOCKS, out4, h->k, st);
+    hipError_t e =
+        comp(h)    ? cdbm::launch_totals_comp(f, h->partials, REDUCE_BLOCKS, out4, h->k, st)
+        : mixed(h) ? cdbm::launch_totals<float>(f, h->partials, REDUCE_BLOCKS, out4, h->k, st)
+                   : cdbm::launch_totals<double>(f, h->partials, REDUCE_BLOCKS, out4, h->k, st);
     return e == hipSuccess ? CDBM_OK : hip_fail(e, "totals launch");
 }
 

@@ -86,17 +86,20 @@ extern "C" {
 int cdbm_step_adjoint(cdbm_handle* h, const void* f_n, const void* lam_np1, void* lam_n,
                       double* dL_dtau, void* stream) {
     if (!h || !f_n || !lam_np1 || !lam_n) return fail(CDBM_EINVAL, "null argument");
+    if (comp(h)) return fail(CDBM_EINVAL, "the adjoint entry points do not take CDBM_MIXED_COMP");
     return step_adjoint_entry(h, f_n, nullptr, lam_np1, lam_n, dL_dtau, stream);
 }
 
 int cdbm_step_adjoint_stage(cdbm_handle* h, const void* f_n, const void* f1,
                             const void* lam_np1, void* lam_n, double* dL_dtau, void* stream) {
     if (!h || !f_n || !f1 || !lam_np1 || !lam_n) return fail(CDBM_EINVAL, "null argument");
+    if (comp(h)) return fail(CDBM_EINVAL, "the adjoint entry points do not take CDBM_MIXED_COMP");
     return step_adjoint_entry(h, f_n, f1, lam_np1, lam_n, dL_dtau, stream);
 }
 
 int cdbm_tau_collect(cdbm_handle* h, double* dL_dtau, void* stream) {
     if (!h || !dL_dtau) return fail(CDBM_EINVAL, "null argument");
+    if (comp(h)) return fail(CDBM_EINVAL, "the adjoint entry points do not take CDBM_MIXED_COMP");
     int rc = check_device(h);
     if (rc != CDBM_OK) return rc;
     const int nb = stage_adjoint_blocks(h->k);
@@ -110,6 +113,7 @@ int cdbm_init_adjoint(cdbm_handle* h, const double* rho, const double* ux, const
                       double* g_uy, double* g_T, void* stream) {
     if (!h || !rho || !ux || !uy || !T || !lam_f0 || !g_rho || !g_ux || !g_uy || !g_T)
         return fail(CDBM_EINVAL, "null argument");
+    if (comp(h)) return fail(CDBM_EINVAL, "the adjoint entry points do not take CDBM_MIXED_COMP");
     int rc = check_device(h);
     if (rc != CDBM_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -124,6 +128,7 @@ int cdbm_moments_adjoint(cdbm_handle* h, const void* f, const double* g_rho, con
                          const double* g_uy, const double* g_T, void* lam_f, void* stream) {
     if (!h || !f || !g_rho || !g_ux || !g_uy || !g_T || !lam_f)
         return fail(CDBM_EINVAL, "null argument");
+    if (comp(h)) return fail(CDBM_EINVAL, "the adjoint entry points do not take CDBM_MIXED_COMP");
     if (overlaps(lam_f, sizeof(double) * (size_t)NV * (size_t)h->cells, f, h->fbytes))
         return fail(CDBM_EINVAL, "lam_f overlaps f");
     int rc = check_device(h);

@@ -339,6 +339,10 @@ int cdbm_batch_create(const cdbm_params* per_grid, int32_t ngrids, const int64_t
     b->k.resize(ngrids);
     b->off.assign(f_offsets, f_offsets + ngrids);
     b->precision = per_grid[0].precision;
+    if (b->precision == CDBM_MIXED_COMP) {
+        delete b;
+        return fail(CDBM_EINVAL, "the batched form does not take CDBM_MIXED_COMP");
+    }
     char buf[160];
     for (int g = 0; g < ngrids; ++g) {
         const cdbm_params& q = per_grid[g];

@@ -67,6 +67,11 @@ struct cdbm_handle {
 
 namespace cdbm {
 inline bool mixed(const cdbm_handle* h) { return h->p.precision == CDBM_MIXED; }
+// The compensated mixed form: float f plus the conserved-moment residual.
+inline bool comp(const cdbm_handle* h) { return h->p.precision == CDBM_MIXED_COMP; }
+// Planes of a state: the 16 distributions, plus the four residual planes of
+// the compensated form.
+inline int state_planes(int precision) { return precision == CDBM_MIXED_COMP ? NV + 4 : NV; }
 int check_device(const cdbm_handle* h);
 int ensure_buffer(cdbm_handle* h, void** buf);
 int check_fields_range(int* flag, const double* rho, const double* ux, const double* uy,

@@ -59,7 +59,8 @@ extern "C" int cdbm_conserved_totals_static(const cdbm_params* p, const void* f,
     rc = scratch_address(dev, &part);
     if (rc != CDBM_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
-    e = p->precision == CDBM_MIXED ? launch_totals<float>(f, part, REDUCE_BLOCKS, out4, K, st)
-                                   : launch_totals<double>(f, part, REDUCE_BLOCKS, out4, K, st);
+    e = p->precision == CDBM_MIXED_COMP ? launch_totals_comp(f, part, REDUCE_BLOCKS, out4, K, st)
+        : p->precision == CDBM_MIXED    ? launch_totals<float>(f, part, REDUCE_BLOCKS, out4, K, st)
+                                        : launch_totals<double>(f, part, REDUCE_BLOCKS, out4, K, st);
     return e == hipSuccess ? CDBM_OK : hip_fail(e, "totals launch");
 }

@@ -47,7 +47,75 @@ __device__ __forceinline__ void load_cell(const S* __restrict__ f, int64_t cells
     for (int i = 0; i < NV; ++i) fd[i] = (double)f[i * cells + c];
 }
 
-template <typename S>
+// The compensated mixed form (CDBM_MIXED_COMP): a state holds the 16 planes
+// of f in float and then the four planes of r, the part of the cell's
+// (rho, j_x, j_y, 2E) that float storage of f rounded off.
+
+// (rho, j_x, j_y, 2E) of the distributions whose parity combinations are g.
+__device__ __forceinline__ void conserved_of(const Parity& g, const KParams& K, double out[4]) {
+    out[0] = ((g.ee[0] + g.ee[1]) + (g.ee[2] + g.ee[3])) + (g.ee[4] + g.ee[5]);
+    double jx = 0.0, jy = 0.0, e2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        jx = fma(K.jx[c], g.oe[c], jx);
+        jy = fma(K.jy[c], g.eo[c], jy);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e2 = fma(K.en[c], g.ee[c], e2);
+    out[1] = jx;
+    out[2] = jy;
+    out[3] = e2;
+}
+
+// Macroscopic fields of a compensated cell: the conserved moments of its
+// stored f plus its residual r.
+__device__ __forceinline__ Macro macro_compensated(const Parity& g, const double r[4],
+                                                   const KParams& K) {
+    double q[4];
+    conserved_of(g, K, q);
+    const double rho = q[0] + r[0];
+    Macro m;
+    m.rho = rho;
+    m.ux = (q[1] + r[1]) / rho;
+    m.uy = (q[2] + r[2]) / rho;
+    m.T = ((q[3] + r[3]) / rho - (m.ux * m.ux + m.uy * m.uy)) * K.inv_a;
+    return m;
+}
+
+__device__ __forceinline__ void load_residual(const float* __restrict__ f, int64_t cells,
+                                              int64_t c, double r[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = (double)f[(NV + k) * cells + c];
+}
+
+// Compensated initial state: f = f^eq rounded to float, r = the conserved
+// moments of what the rounding removed.
+__global__ void __launch_bounds__(256) k_init_comp(const double* __restrict__ rho,
+                                                   const double* __restrict__ ux,
+                                                   const double* __restrict__ uy,
+                                                   const double* __restrict__ T,
+                                                   float* __restrict__ f, KParams K,
+                                                   int64_t cells) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    Macro m{rho[c], ux[c], uy[c], T[c]};
+    double feq[NV], lost[NV];
+    equilibrium(m, K, K.a, feq);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const float v = (float)feq[i];
+        f[i * cells + c] = v;
+        lost[i] = feq[i] - (double)v;
+    }
+    Parity g;
+    to_parity(lost, g);
+    double r[4];
+    conserved_of(g, K, r);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) f[(NV + k) * cells + c] = (float)r[k];
+}
+
+template <typename S, bool COMP = false>
 __global__ void __launch_bounds__(256) k_moments(const S* __restrict__ f, double* __restrict__ rho,
                                                  double* __restrict__ ux, double* __restrict__ uy,
                                                  double* __restrict__ T, KParams K, int64_t cells) {
@@ -57,7 +125,14 @@ __global__ void __launch_bounds__(256) k_moments(const S* __restrict__ f, double
     load_cell(f, cells, c, fd);
     Parity g;
     to_parity(fd, g);
-    const Macro m = macro_from_parity(g, K, K.inv_a);
+    Macro m;
+    if constexpr (COMP) {
+        double r[4];
+        load_residual(f, cells, c, r);
+        m = macro_compensated(g, r, K);
+    } else {
+        m = macro_from_parity(g, K, K.inv_a);
+    }
     rho[c] = m.rho;
     ux[c] = m.ux;
     uy[c] = m.uy;
@@ -67,7 +142,8 @@ __global__ void __launch_bounds__(256) k_moments(const S* __restrict__ f, double
 // Eqs. (8)-(11): sum_i (f_i - f_i^eq) Psi_r(v_i - u), rows r = 5..16.
 // RAW: the measures of the raw-moment construction, Psi_r(v_i) at the raw
 // velocities (same f^eq).
-template <typename S, bool RAW>
+// COMP: f^eq of the compensated moments, f the stored float distributions.
+template <typename S, bool RAW, bool COMP = false>
 __global__ void __launch_bounds__(256) k_tne(const S* __restrict__ f, double* __restrict__ out,
                                              KParams K, int64_t cells) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -76,7 +152,14 @@ __global__ void __launch_bounds__(256) k_tne(const S* __restrict__ f, double* __
     load_cell(f, cells, c, fd);
     Parity g;
     to_parity(fd, g);
-    const Macro m = macro_from_parity(g, K, K.inv_a);
+    Macro m;
+    if constexpr (COMP) {
+        double r[4];
+        load_residual(f, cells, c, r);
+        m = macro_compensated(g, r, K);
+    } else {
+        m = macro_from_parity(g, K, K.inv_a);
+    }
     double feq[NV];
     equilibrium(m, K, K.a, feq);
     double acc[12];
@@ -106,7 +189,7 @@ __global__ void __launch_bounds__(256) k_tne(const S* __restrict__ f, double* __
 }
 
 // Per-block partial sums of (rho, j_x, j_y, 2E); block count is fixed.
-template <typename S>
+template <typename S, bool COMP = false>
 __global__ void __launch_bounds__(256) k_totals_partial(const S* __restrict__ f, KParams K,
                                                         int64_t cells, double* __restrict__ part) {
     __shared__ double red[4][256];
@@ -121,6 +204,12 @@ __global__ void __launch_bounds__(256) k_totals_partial(const S* __restrict__ f,
             acc[1] = fma(fd[i], K.vx[i], acc[1]);
             acc[2] = fma(fd[i], K.vy[i], acc[2]);
             acc[3] = fma(fd[i], K.vx[i] * K.vx[i] + K.vy[i] * K.vy[i] + K.eta2[i], acc[3]);
+        }
+        if constexpr (COMP) {
+            double r[4];
+            load_residual(f, cells, c, r);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] += r[k];
         }
     }
     for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = acc[k];
@@ -197,6 +286,90 @@ __global__ void __launch_bounds__(256) k_stage(const S* __restrict__ fin, const 
     }
 }
 
+// One Runge-Kutta stage of the compensated form, one cell per thread: f is
+// read from float storage and every term is formed in double, as in the
+// FP64 form:
+//   STAGE2 == false:  y = f + A,              out = round(y + C),
+//                     r_out = r + m(y - out)
+//   STAGE2 == true:   y = base/2 + f/2 + A,   out = round(y + C),
+//                     r_out = r_base/2 + r/2 + m(y - out)
+// where A is the stage's advection term dt (-v . grad f) of Eqs. (12)-(20)
+// and C its relaxation term -dt (f - f^eq)/tau of Eq. (1) (both halved in
+// the second stage), f^eq is that of the compensated moments m(f) + r, and
+// m(.) is (rho, j_x, j_y, 2E) of a set of 16 values.  The conserved moments
+// m(f) + r of the output are those of the stage's combination without C
+// (the advection flux changes them, the relaxation does not); C itself
+// carries dt/tau of r into f.  The differences of the NND stencil are exact
+// in double (two floats of like size), so the advection terms of
+// neighbouring cells cancel in the grid sums to FP64 rounding.
+template <bool STAGE2>
+__global__ void __launch_bounds__(256) k_stage_comp(const float* __restrict__ fin,
+                                                    const float* __restrict__ base,
+                                                    float* __restrict__ fout,
+                                                    const KParams* __restrict__ Kd) {
+    const KParams& K = *Kd;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= K.nx || y >= K.ny) return;
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    GlobalLd<float> ld;
+    ld.f = fin;
+    ld.cells = cells;
+    ld.nx = K.nx;
+#pragma unroll
+    for (int o = -2; o <= 2; ++o) {
+        ld.xs[o + 2] = wrap_or_clamp(x + o, K.nx, K.bcx);
+        ld.ys[o + 2] = wrap_or_clamp(y + o, K.ny, K.bcy);
+    }
+    const int64_t c = (int64_t)y * K.nx + x;
+    float f[NV];
+    double fd[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        f[i] = ld(i, 0, 0);
+        fd[i] = (double)f[i];
+    }
+    double r[4];
+    load_residual(fin, cells, c, r);
+    Parity g;
+    to_parity(fd, g);
+    const Macro m = macro_compensated(g, r, K);
+    double neq[NV];
+    nonequilibrium(g, m, K, K.a, neq);
+    const double nza = K.nzq[STAGE2][0], nzd = K.nzq[STAGE2][1];
+    auto ldd = [&](int i, int ox, int oy) { return (double)ld(i, ox, oy); };
+    double lost[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const double cx = STAGE2 ? K.cxh[i] : K.cx[i];
+        const double cy = STAGE2 ? K.cyh[i] : K.cy[i];
+        double adv = 0.0;
+        if (SX[i] > 0) adv = cx * nnd_pos<double>(ldd(i, -2, 0), ldd(i, -1, 0), fd[i], ldd(i, 1, 0));
+        else if (SX[i] < 0)
+            adv = cx * nnd_neg<double>(ldd(i, -1, 0), fd[i], ldd(i, 1, 0), ldd(i, 2, 0));
+        if (SY[i] > 0) adv += cy * nnd_pos<double>(ldd(i, 0, -2), ldd(i, 0, -1), fd[i], ldd(i, 0, 1));
+        else if (SY[i] < 0)
+            adv += cy * nnd_neg<double>(ldd(i, 0, -1), fd[i], ldd(i, 0, 1), ldd(i, 0, 2));
+        const double coll = ((i & 4) ? nzd : nza) * neq[i];
+        double yv = adv;
+        if (STAGE2) yv += 0.5 * fd[i] + 0.5 * (double)base[i * cells + c];
+        else yv += fd[i];
+        const float o = (float)(yv + coll);
+        fout[i * cells + c] = o;
+        lost[i] = yv - (double)o;
+    }
+    Parity gl;
+    to_parity(lost, gl);
+    double dm[4];
+    conserved_of(gl, K, dm);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double rk = r[k];
+        if (STAGE2) rk = 0.5 * (double)base[(NV + k) * cells + c] + 0.5 * rk;
+        fout[(NV + k) * cells + c] = (float)(rk + dm[k]);
+    }
+}
+
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -264,6 +437,55 @@ hipError_t launch_stage(const void* fin, const void* base, void* fout, bool stag
     else
         hipLaunchKernelGGL((k_stage<S, false>), grid, dim3(256), 0, st, (const S*)fin,
                            (const S*)base, (S*)fout, Kd);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_comp(const double* rho, const double* ux, const double* uy,
+                            const double* T, void* f, const KParams& K, hipStream_t st) {
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    hipLaunchKernelGGL(k_init_comp, dim3(blocks_for(cells, 256)), dim3(256), 0, st, rho, ux, uy,
+                       T, (float*)f, K, cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments_comp(const void* f, double* rho, double* ux, double* uy, double* T,
+                               const KParams& K, hipStream_t st) {
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    hipLaunchKernelGGL((k_moments<float, true>), dim3(blocks_for(cells, 256)), dim3(256), 0, st,
+                       (const float*)f, rho, ux, uy, T, K, cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_tne_comp(const void* f, double* out12, bool raw, const KParams& K,
+                           hipStream_t st) {
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    if (raw)
+        hipLaunchKernelGGL((k_tne<float, true, true>), dim3(blocks_for(cells, 256)), dim3(256), 0,
+                           st, (const float*)f, out12, K, cells);
+    else
+        hipLaunchKernelGGL((k_tne<float, false, true>), dim3(blocks_for(cells, 256)), dim3(256), 0,
+                           st, (const float*)f, out12, K, cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_totals_comp(const void* f, double* partials, int nblocks, double* out4,
+                              const KParams& K, hipStream_t st) {
+    const int64_t cells = (int64_t)K.nx * K.ny;
+    hipLaunchKernelGGL((k_totals_partial<float, true>), dim3(nblocks), dim3(256), 0, st,
+                       (const float*)f, K, cells, partials);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partials, nblocks, 4, out4);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_comp(const void* fin, const void* base, void* fout, bool stage2,
+                             const KParams& K, const KParams* Kd, hipStream_t st) {
+    const dim3 grid(blocks_for(K.nx, 64), blocks_for(K.ny, 4));
+    if (stage2)
+        hipLaunchKernelGGL((k_stage_comp<true>), grid, dim3(256), 0, st, (const float*)fin,
+                           (const float*)base, (float*)fout, Kd);
+    else
+        hipLaunchKernelGGL((k_stage_comp<false>), grid, dim3(256), 0, st, (const float*)fin,
+                           (const float*)base, (float*)fout, Kd);
     return hipGetLastError();
 }
 

@@ -28,6 +28,19 @@ template <typename S>
 hipError_t launch_stage(const void* fin, const void* base, void* fout, bool stage2,
                         const KParams& K, const KParams* Kd, hipStream_t st);
 
+// The compensated mixed form (CDBM_MIXED_COMP): float states of 20 planes,
+// the 16 of f and the four of the conserved-moment residual r.
+hipError_t launch_init_comp(const double* rho, const double* ux, const double* uy,
+                            const double* T, void* f, const KParams& K, hipStream_t st);
+hipError_t launch_moments_comp(const void* f, double* rho, double* ux, double* uy, double* T,
+                               const KParams& K, hipStream_t st);
+hipError_t launch_tne_comp(const void* f, double* out12, bool raw, const KParams& K,
+                           hipStream_t st);
+hipError_t launch_totals_comp(const void* f, double* partials, int nblocks, double* out4,
+                              const KParams& K, hipStream_t st);
+hipError_t launch_stage_comp(const void* fin, const void* base, void* fout, bool stage2,
+                             const KParams& K, const KParams* Kd, hipStream_t st);
+
 // Compute units of the current device (cached per device; 256 if the query
 // fails).
 int device_cus();

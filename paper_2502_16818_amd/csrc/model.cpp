@@ -130,8 +130,8 @@ int build_params(const cdbm_params& p, KParams& k, std::string& err) {
         err = "bc_x and bc_y must be CDBM_PERIODIC or CDBM_ZERO_GRADIENT";
         return CDBM_EINVAL;
     }
-    if (p.precision != CDBM_FP64 && p.precision != CDBM_MIXED) {
-        err = "precision must be CDBM_FP64 or CDBM_MIXED";
+    if (p.precision != CDBM_FP64 && p.precision != CDBM_MIXED && p.precision != CDBM_MIXED_COMP) {
+        err = "precision must be CDBM_FP64, CDBM_MIXED or CDBM_MIXED_COMP";
         return CDBM_EINVAL;
     }
     if (p.step_form < CDBM_STEP_AUTO || p.step_form > CDBM_STEP_FUSED2) {
@@ -141,6 +141,12 @@ int build_params(const cdbm_params& p, KParams& k, std::string& err) {
     }
     if (p.step_form == CDBM_STEP_FUSED2 && p.precision != CDBM_MIXED) {
         err = "CDBM_STEP_FUSED2 needs CDBM_MIXED: four rings of FP64 rows do not fit the LDS";
+        return CDBM_EINVAL;
+    }
+    if (p.precision == CDBM_MIXED_COMP && p.step_form != CDBM_STEP_AUTO &&
+        p.step_form != CDBM_STEP_SPLIT) {
+        err = "CDBM_MIXED_COMP runs as two single-stage launches: step_form must be "
+              "CDBM_STEP_AUTO or CDBM_STEP_SPLIT";
         return CDBM_EINVAL;
     }
 

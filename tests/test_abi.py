@@ -146,3 +146,21 @@ def test_two_step_form_needs_fp32_storage(lib):
     h = ctypes.c_void_p()
     assert lib.cdbm_create(ctypes.byref(p), ctypes.byref(h)) == -1
     assert b"CDBM_STEP_FUSED2" in lib.cdbm_last_error()
+
+
+@pytest.mark.parametrize("form", [1, 3])
+def test_compensated_form_runs_split_only(lib, form):
+    """CDBM_MIXED_COMP takes CDBM_STEP_AUTO or CDBM_STEP_SPLIT only."""
+    p = _params(step_form=form, precision=2)
+    h = ctypes.c_void_p()
+    assert lib.cdbm_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    assert not h.value and b"CDBM_MIXED" in lib.cdbm_last_error()
+
+
+def test_batch_rejects_the_compensated_form(lib):
+    P = type(_params())
+    b = ctypes.c_void_p()
+    one = (P * 1)(_params(precision=2))
+    off = (ctypes.c_int64 * 1)(0)
+    assert lib.cdbm_batch_create(one, 1, off, ctypes.byref(b)) == -1
+    assert not b.value and b"CDBM_MIXED_COMP" in lib.cdbm_last_error()

@@ -1,0 +1,240 @@
+"""The compensated mixed form (CDBM_MIXED_COMP): f stored in FP32 as in the
+mixed form, every stage's arithmetic in FP64, plus a per-cell FP32 residual
+r of the conserved moments (rho, j_x, j_y, 2E) that rounding f to FP32
+removed.  The cell's conserved moments are sum_i f_i psi_i + r, so changes
+of mass, momentum and energy far below an FP32 unit of f per step are kept
+instead of rounded away.
+
+Checks, through the C ABI: the initial state reproduces the fields to FP64
+rounding; 20 steps against the FP64 oracle on the forward-parity grids;
+grid totals conserved to FP64 rounding on periodic grids; the 64 x 64
+vortex over its 10000 steps against the oracle reference of
+tests/golden/long_runs.npz; and the 512 x 512 vortex of the 10000-step
+workload, whose viscous kinetic-energy decay the plain mixed form loses."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cdbm as C
+import workloads as W
+from helpers import field_errors, oracle_after, to_np
+
+pytestmark = pytest.mark.gpu
+
+FP64, MIXED, COMP = 0, 1, 2   # CDBM_FP64, CDBM_MIXED, CDBM_MIXED_COMP of include/cdbm.h
+AUTO, FUSED, SPLIT, FUSED2 = 0, 1, 2, 3
+
+
+def _solver(run, precision, form=AUTO):
+    from paper_2502_16818_amd import Solver
+    print(f"[case] {run.name} {run.nx}x{run.ny} precision={precision} step_form={form}",
+          flush=True)
+    return Solver.from_run(run, precision, form)
+
+
+def _cases():
+    rnd = W.random_periodic(137, 23, seed=1, dt=1e-4, tau=2e-4)
+    acl = W.lax_acoustic_2d(130, ny=19, seed=2)
+    zg = W.random_periodic(61, 9, seed=5, dt=1e-4, tau=1e-4)
+    zg.bc_x = W.ZERO_GRADIENT
+    zg.bc_y = W.ZERO_GRADIENT
+    lax = W.lax_tube(nx=150, dx=2e-3)
+    one = W.random_periodic(1, 1, seed=7, dt=1e-4, tau=1e-4)
+    return [rnd, acl, zg, lax, one]
+
+
+def test_state_layout_and_rejected_forms():
+    from paper_2502_16818_amd import CdbmError
+    run = _cases()[0]
+    s = _solver(run, COMP)
+    f = s.init(run.rho, run.ux, run.uy, run.T)
+    assert f.shape == (20, run.ny, run.nx) and f.dtype == torch.float32
+    with pytest.raises(CdbmError):
+        s.step_keep_stage(f)
+    with pytest.raises(CdbmError):
+        s.step_adjoint(f, torch.zeros((16, run.ny, run.nx), dtype=torch.float64, device="cuda"))
+    s.close()
+    for form in (FUSED, FUSED2):
+        with pytest.raises(CdbmError):
+            _solver(run, COMP, form)
+
+
+@pytest.mark.parametrize("run", _cases(), ids=lambda r: r.name)
+def test_init_reproduces_the_fields(run):
+    """f^eq rounded to FP32 plus the residual of what the rounding removed:
+    the moments give back rho, u and T to the FP64 form's own bar of 1e-12
+    (its f^eq contraction with the inverse of M0, condition numbers up to
+    4e3, leaves 1e-13; the plain mixed form: FP32 rounding, about 1e-7)."""
+    s = _solver(run, COMP)
+    f = s.init(run.rho, run.ux, run.uy, run.T)
+    got = [to_np(a) for a in s.moments(f)]
+    want = [np.asarray(a, dtype=np.float64).reshape(run.ny, run.nx)
+            for a in (run.rho, run.ux, run.uy, run.T)]
+    umax = max(np.abs(want[1]).max(), np.abs(want[2]).max(), 1e-2)
+    errs = {n: float(np.abs(g - w).max() / (umax if n in ("ux", "uy") else np.abs(w).max()))
+            for n, g, w in zip(("rho", "ux", "uy", "T"), got, want)}
+    print(errs)
+    assert max(errs.values()) <= 1e-12
+    # the FP32 planes of f are the plain mixed form's initial state
+    m = _solver(run, MIXED)
+    fm = m.init(run.rho, run.ux, run.uy, run.T)
+    assert torch.equal(f[:16], fm)
+    s.close()
+    m.close()
+
+
+@pytest.mark.parametrize("run", _cases(), ids=lambda r: r.name)
+def test_steps_against_fp64_oracle(run):
+    """20 steps against the FP64 oracle, with the plain mixed form's errors
+    on the same run printed beside them (mixed: up to 2.8e-6 on rho and T,
+    1.3e-5 on u).  Compensated, measured: up to 8e-8 on rho and T and 4.8e-7
+    on u (f itself is still rounded to FP32, and the flow carries that
+    rounding into the non-conserved parts and from there into u and T);
+    bounds 4e-7 and 2.5e-6, and f within 3e-6 of max |f|."""
+    n = 20
+    p, ref = oracle_after(run, n)
+    want = [a.numpy() for a in C.fields(ref, p)]
+    umax = max(np.abs(want[1]).max(), np.abs(want[2]).max(), 1e-2)
+    errs = {}
+    for prec in (MIXED, COMP):
+        s = _solver(run, prec)
+        f = s.init(run.rho, run.ux, run.uy, run.T)
+        out = s.step(f, nsteps=n)
+        errs[prec] = field_errors([to_np(a) for a in s.moments(out)], want, u_scale=umax)
+        if prec == COMP:
+            fmax = float(ref.abs().max())
+            ferr = float(np.abs(to_np(out[:16]) - ref.numpy()).max()) / fmax
+        s.close()
+    print(f"  mixed {errs[MIXED]}\n  compensated {errs[COMP]}; f {ferr:.2e} of max|f|")
+    e = errs[COMP]
+    assert e["rho"] < 4e-7 and e["T"] < 4e-7
+    assert e["ux"] < 2.5e-6 and e["uy"] < 2.5e-6
+    assert ferr < 3e-6
+
+
+def test_split_and_auto_forms_are_bitwise_equal():
+    run = _cases()[0]
+    outs = []
+    for form in (AUTO, SPLIT):
+        s = _solver(run, COMP, form)
+        f = s.init(run.rho, run.ux, run.uy, run.T)
+        outs.append(s.step(f, nsteps=9))
+        s.close()
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_graph_replays_match_single_steps():
+    """70 steps in one call (two replays of the captured 32-step graph)
+    equal 70 single-step calls bit for bit."""
+    run = W.random_periodic(96, 40, seed=9, dt=1e-4, tau=2e-4)
+    s = _solver(run, COMP)
+    f = s.init(run.rho, run.ux, run.uy, run.T)
+    a = s.step(f, nsteps=70)
+    b = f.clone()
+    for _ in range(70):
+        b = s.step(b, nsteps=1)
+    assert torch.equal(a, b)
+    s.close()
+
+
+def test_totals_conserved_to_fp64_rounding():
+    """Periodic grids conserve mass, momentum and energy exactly in exact
+    arithmetic (the NND terms of neighbouring cells cancel in the sums).  The
+    compensated form carries the conserved moments to FP64 rounding (bound
+    1e-13 of each total's scale over 300 steps); the plain mixed form, whose
+    advection terms are FP32 and whose f is rounded without compensation,
+    is printed beside it."""
+    run = W.random_periodic(96, 80, seed=4, dt=1e-4, tau=2e-4)
+    drift = {}
+    for prec in (MIXED, COMP):
+        s = _solver(run, prec)
+        f = s.init(run.rho, run.ux, run.uy, run.T)
+        t0 = to_np(s.totals(f))
+        g = s.step(f, nsteps=300)
+        t1 = to_np(s.totals(g))
+        scale = np.array([abs(t0[0]), abs(t0[0]) * 0.3, abs(t0[0]) * 0.3, abs(t0[3])])
+        drift[prec] = np.abs(t1 - t0) / scale
+        s.close()
+    print(f"  relative drift of the totals: mixed {drift[MIXED]}, compensated {drift[COMP]}")
+    assert drift[COMP].max() <= 1e-13
+
+
+def test_static_totals_equal_handle_totals():
+    from paper_2502_16818_amd import load, make_params
+    import ctypes
+    run = _cases()[1]
+    s = _solver(run, COMP)
+    f = s.step(s.init(run.rho, run.ux, run.uy, run.T), nsteps=3)
+    a = s.totals(f)
+    b = torch.empty(4, dtype=torch.float64, device="cuda")
+    p = make_params(run.nx, run.ny, run.dx, run.dy, run.dt, run.tau, run.gamma, run.v, run.eta,
+                    run.bc_x, run.bc_y, COMP)
+    rc = load().cdbm_conserved_totals_static(ctypes.byref(p), f.data_ptr(), b.data_ptr(),
+                                             torch.cuda.current_stream().cuda_stream)
+    assert rc == 0
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    s.close()
+
+
+def _golden_tg64():
+    path = os.path.join(os.path.dirname(__file__), "golden", "long_runs.npz")
+    with np.load(path) as z:
+        meta = json.loads(str(z["meta"]))
+        return meta["tg_64"], {q: z[f"tg_64.{q}"] for q in ("rho", "ux", "uy", "T")}
+
+
+def test_taylor_green_64_full_run_against_oracle():
+    """The [0, 2 pi)^2 vortex at 64 x 64 over its 10000 steps against the
+    oracle reference (relative L2 per field, u against max |u|).  The plain
+    mixed form's errors there are 1.1e-5 (rho), 8.7e-5 (u), 7.7e-6 (T), most
+    of it the lost viscous decay; the compensated form measured 6e-9 (rho),
+    5.6e-8 (u), 4e-9 (T) and is gated at 3e-7 on every field."""
+    meta, want = _golden_tg64()
+    run = W.taylor_green_2pi(n=64)
+    assert meta["steps"] == run.steps and meta["nx"] == run.nx
+    s = _solver(run, COMP)
+    g = s.step(s.init(run.rho, run.ux, run.uy, run.T), nsteps=run.steps)
+    got = [to_np(a) for a in s.moments(g)]
+    s.close()
+    umax = float(np.sqrt(want["ux"] ** 2 + want["uy"] ** 2).max())
+    errs = field_errors(got, [want[q] for q in ("rho", "ux", "uy", "T")], u_scale=umax)
+    print(f"  compensated tg_64 after {run.steps} steps: {errs}")
+    assert max(errs.values()) <= 3e-7
+
+
+def _kinetic_energy(s, f):
+    rho, ux, uy, _ = s.moments(f)
+    return float((rho * (ux ** 2 + uy ** 2)).sum()), ux.clone(), uy.clone()
+
+
+def test_taylor_green_512_keeps_the_viscous_decay():
+    """The 512 x 512 vortex workload (10000 steps to t = 1).  The FP64
+    kinetic-energy drop is the viscous 4.0e-4 plus the scheme's own
+    dissipation (5.2e-4 in all); the plain mixed form keeps about a tenth of
+    it (5.6e-5).  The compensated form's drop is gated within 1 % of the
+    FP64 drop (measured 0.004 %) and its velocity field within 2e-5
+    (relative L2, against U0 = 0.1; measured 1.1e-5) of the FP64 one (the
+    plain mixed form: 2.8e-4)."""
+    run = W.taylor_green_2pi()
+    res = {}
+    for prec in (FP64, MIXED, COMP):
+        s = _solver(run, prec)
+        f = s.init(run.rho, run.ux, run.uy, run.T)
+        ke0, _, _ = _kinetic_energy(s, f)
+        ke1, ux, uy = _kinetic_energy(s, s.step(f, nsteps=run.steps))
+        res[prec] = (1.0 - ke1 / ke0, ux, uy)
+        s.close()
+    d64 = res[FP64][0]
+
+    def du(prec):
+        return float(torch.sqrt(((res[prec][1] - res[FP64][1]) ** 2 +
+                                 (res[prec][2] - res[FP64][2]) ** 2).mean())) / 0.1
+
+    print(f"  KE drop: fp64 {d64:.4e}, mixed {res[MIXED][0]:.4e}, compensated {res[COMP][0]:.4e}; "
+          f"velocity vs fp64: mixed {du(MIXED):.2e}, compensated {du(COMP):.2e}")
+    assert abs(res[COMP][0] - d64) <= 0.01 * d64
+    assert du(COMP) <= 2e-5
