@@ -305,14 +305,19 @@ int cdbm_batch_step(cdbm_batch* b, const void* f_in, void* f_out, int32_t nsteps
  *   CDBM_BATCH_ROW_PIECES: every grid cut into row pieces of about
  *     piece_rows rows; the units (grid, piece, strip) are taken in order from
  *     one counter per XCD, so that the blocks of an XCD work on neighbouring
- *     strips of the same rows at the same time.
- * `reserved` must be 0. */
+ *     strips of the same rows at the same time, and a block whose XCD's
+ *     units are used up takes units from the other XCDs' counters.  With
+ *     tail_rows > 0 the last tail_rows rows of every grid taller than twice
+ *     that are cut off the pieces and taken, one unit per strip, after the
+ *     pieces of the same counter, so that each counter ends with small
+ *     units.
+ * tail_rows must be 0 in the contiguous layout. */
 enum { CDBM_BATCH_CONTIGUOUS = 0, CDBM_BATCH_ROW_PIECES = 1 };
 typedef struct cdbm_batch_launch {
     int32_t layout;
     int32_t fill_rows;    /* CONTIGUOUS: 0 .. 1024 */
     int32_t piece_rows;   /* ROW_PIECES: 16 .. 65536 */
-    int32_t reserved;
+    int32_t tail_rows;    /* ROW_PIECES: 0, or 8 .. 65536 */
 } cdbm_batch_launch;
 
 /* The batch's current launch layout. */
@@ -326,8 +331,10 @@ int cdbm_batch_set_launch(cdbm_batch* b, const cdbm_batch_launch* l);
  * architecture, the precision form, and floor(log2) of the batch's cell and
  * grid counts) in the JSON cache file `cache_path` (NULL: no cache) and
  * applies the stored layout; otherwise times the candidate layouts (the
- * contiguous split with fill_rows 0, 14, 28 and row pieces of 128, 192 and
- * 256 rows; 26 steps each), applies the fastest and adds it to the cache
+ * contiguous split with fill_rows 0, 14, 28; row pieces of 128 and 192
+ * rows; row pieces with tails, (piece_rows, tail_rows) = (160, 64),
+ * (192, 64), (320, 96), (320, 128), (384, 160), (448, 160); 26 steps each),
+ * applies the fastest and adds it to the cache
  * (written through a temporary file; an unwritable cache is skipped).  f_in:
  * a state of the batch (read only); f_out and the batch's scratch buffer are
  * overwritten by the timing steps.  `chosen` (may be NULL) receives the

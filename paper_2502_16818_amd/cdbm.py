@@ -37,10 +37,11 @@ BATCH_CONTIGUOUS, BATCH_ROW_PIECES = 0, 1
 
 class BatchLaunch(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("fill_rows", ctypes.c_int32),
-                ("piece_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("piece_rows", ctypes.c_int32), ("tail_rows", ctypes.c_int32)]
 
     def as_dict(self):
-        return {"layout": self.layout, "fill_rows": self.fill_rows, "piece_rows": self.piece_rows}
+        return {"layout": self.layout, "fill_rows": self.fill_rows, "piece_rows": self.piece_rows,
+                "tail_rows": self.tail_rows}
 
 
 class CdbmError(RuntimeError):
@@ -372,8 +373,8 @@ class Batch:
         return out.as_dict()
 
     def set_launch(self, layout: int = BATCH_CONTIGUOUS, fill_rows: int = 14,
-                   piece_rows: int = 0) -> None:
-        l = BatchLaunch(int(layout), int(fill_rows), int(piece_rows), 0)
+                   piece_rows: int = 0, tail_rows: int = 0) -> None:
+        l = BatchLaunch(int(layout), int(fill_rows), int(piece_rows), int(tail_rows))
         _check(load().cdbm_batch_set_launch(self._b, ctypes.byref(l)), "cdbm_batch_set_launch")
 
     def autotune(self, f_in: torch.Tensor, f_out: torch.Tensor,

@@ -33,10 +33,10 @@ struct cdbm_batch {
     int nblocks = 1;
     bool chunked = false;   // every width and offset is a multiple of the 16-byte chunk
     cdbm_batch_launch launch{CDBM_BATCH_CONTIGUOUS, BATCH_FILL, 0, 0};
-    // row-piece form: unit prefix sums, per-grid (strips, pieces, rows), the
-    // counter ranges and the counters themselves
-    int64_t* d_units = nullptr;
-    int* d_geom = nullptr;
+    // row-piece form: the unit table (four ints per unit), its capacity in
+    // units, the counter ranges and the counters themselves
+    int* d_units = nullptr;
+    int64_t units_cap = 0;
     int64_t* d_range = nullptr;
     int* d_counters = nullptr;
     int nq = 1;
@@ -53,7 +53,6 @@ void release(cdbm_batch* b) {
     if (b->flag) (void)hipFree(b->flag);
     if (b->scratch) (void)hipFree(b->scratch);
     if (b->d_units) (void)hipFree(b->d_units);
-    if (b->d_geom) (void)hipFree(b->d_geom);
     if (b->d_range) (void)hipFree(b->d_range);
     if (b->d_counters) (void)hipFree(b->d_counters);
     delete b;
@@ -65,11 +64,11 @@ hipError_t batch_step_once(const void* ctx, const void* fin, void* fout, hipStre
     if (b->launch.layout == CDBM_BATCH_ROW_PIECES)
         return b->precision == CDBM_MIXED
                    ? launch_batch_step_rows<float>(fin, fout, b->d_k, b->d_off, b->d_units,
-                                                   b->d_geom, b->d_range, b->nq, b->d_counters,
-                                                   b->nblocks, b->chunked, st)
+                                                   b->d_range, b->nq, b->d_counters, b->nblocks,
+                                                   b->chunked, st)
                    : launch_batch_step_rows<double>(fin, fout, b->d_k, b->d_off, b->d_units,
-                                                    b->d_geom, b->d_range, b->nq, b->d_counters,
-                                                    b->nblocks, b->chunked, st);
+                                                    b->d_range, b->nq, b->d_counters, b->nblocks,
+                                                    b->chunked, st);
     return b->precision == CDBM_MIXED
                ? launch_batch_step<float>(fin, fout, b->d_k, b->d_off, b->d_work, n,
                                           b->launch.fill_rows, b->nblocks, b->chunked, st)
@@ -84,6 +83,11 @@ int check_launch(const cdbm_batch_launch& l) {
         return fail(CDBM_EINVAL, "fill_rows must lie in [0, 1024]");
     if (l.layout == CDBM_BATCH_ROW_PIECES && (l.piece_rows < 16 || l.piece_rows > 65536))
         return fail(CDBM_EINVAL, "piece_rows must lie in [16, 65536]");
+    if (l.layout == CDBM_BATCH_ROW_PIECES && l.tail_rows != 0 &&
+        (l.tail_rows < 8 || l.tail_rows > 65536))
+        return fail(CDBM_EINVAL, "tail_rows must be 0 or lie in [8, 65536]");
+    if (l.layout == CDBM_BATCH_CONTIGUOUS && l.tail_rows != 0)
+        return fail(CDBM_EINVAL, "tail_rows must be 0 in the contiguous layout");
     return CDBM_OK;
 }
 
@@ -109,47 +113,85 @@ int apply_launch(cdbm_batch* b, const cdbm_batch_launch& l) {
         e = hipMemcpy(b->d_work, work.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpy of the batch work table");
     } else {
-        std::vector<int64_t> units(n + 1, 0);
-        std::vector<int> geom(3 * n);
-        std::vector<double> weight;   // per unit
+        // units (grid, strip column, first row, end row): each grid's rows
+        // above its tail cut into pieces of about piece_rows rows, strip by
+        // strip within a piece; the tail (the last tail_rows rows of a grid
+        // taller than twice that) as one unit per strip, placed after the
+        // pieces of the range that holds the grid's last piece, so that every
+        // range ends with small units
+        struct Unit {
+            int g, x0, ya, yb;
+        };
+        std::vector<Unit> body;
+        std::vector<int64_t> last(n, -1);   // index in body of each grid's last unit
+        std::vector<std::vector<Unit>> tails(n);
+        double total = 0.0;
         for (int g = 0; g < n; ++g) {
             const int ny = b->p[g].ny;
             const int strips = (b->p[g].nx + tx - 1) / tx;
-            int pieces = std::max(1, (ny + l.piece_rows / 2) / l.piece_rows);
-            const int rows = (ny + pieces - 1) / pieces;
-            pieces = (ny + rows - 1) / rows;
-            geom[3 * g] = strips;
-            geom[3 * g + 1] = pieces;
-            geom[3 * g + 2] = rows;
-            units[g + 1] = units[g] + (int64_t)strips * pieces;
+            const int tail = (l.tail_rows > 0 && ny > 2 * l.tail_rows) ? l.tail_rows : 0;
+            const int nb = ny - tail;
+            int pieces = std::max(1, (nb + l.piece_rows / 2) / l.piece_rows);
+            const int rows = (nb + pieces - 1) / pieces;
+            pieces = (nb + rows - 1) / rows;
             for (int p = 0; p < pieces; ++p) {
-                const int len = std::min(ny, (p + 1) * rows) - p * rows;
-                for (int s = 0; s < strips; ++s) weight.push_back(len + BATCH_FILL);
+                const int ya = p * rows, yb = std::min(nb, ya + rows);
+                for (int s = 0; s < strips; ++s) body.push_back(Unit{g, s * tx, ya, yb});
+                total += (double)strips * (yb - ya + BATCH_FILL);
             }
+            last[g] = (int64_t)body.size() - 1;
+            for (int s = 0; tail > 0 && s < strips; ++s) tails[g].push_back(Unit{g, s * tx, nb, ny});
+            total += (double)tails[g].size() * (tail + BATCH_FILL);
         }
-        if (units[n] >= (int64_t(1) << 31)) return fail(CDBM_EINVAL, "too many work units");
+        if ((int64_t)body.size() >= (int64_t(1) << 30)) return fail(CDBM_EINVAL, "too many work units");
         const int nq = std::max(1, std::min(8, b->nblocks));
-        std::vector<int64_t> range(nq + 1, units[n]);
-        double total = 0.0;
-        for (double w : weight) total += w;
+        // cut the pieces into nq ranges of about equal weight, a grid's tail
+        // counted with its last piece; then each range's pieces followed by
+        // the tails of the grids whose last piece it holds
+        std::vector<Unit> table;
+        table.reserve(body.size() + 64);
+        std::vector<int64_t> range(nq + 1, 0);
         double acc = 0.0;
-        int k = 1;
-        range[0] = 0;
-        for (int64_t u = 0; u < units[n] && k < nq; ++u) {
-            acc += weight[u];
-            while (k < nq && acc >= total * k / nq) range[k++] = u + 1;
+        int k = 0;
+        std::vector<int> ended;   // grids whose last piece the current range holds
+        auto close_range = [&]() {
+            for (int g : ended) table.insert(table.end(), tails[g].begin(), tails[g].end());
+            ended.clear();
+            range[++k] = (int64_t)table.size();
+        };
+        for (int64_t u = 0; u < (int64_t)body.size(); ++u) {
+            const Unit& t = body[u];
+            table.push_back(t);
+            acc += t.yb - t.ya + BATCH_FILL;
+            if (last[t.g] == u) {
+                ended.push_back(t.g);
+                acc += (double)tails[t.g].size() * (l.tail_rows + BATCH_FILL);
+            }
+            if (k < nq - 1 && acc >= total * (k + 1) / nq) close_range();
         }
-        if (!b->d_units) {
-            if (hipMalloc(&b->d_units, sizeof(int64_t) * (n + 1)) != hipSuccess ||
-                hipMalloc(&b->d_geom, sizeof(int) * 3 * n) != hipSuccess ||
-                hipMalloc(&b->d_range, sizeof(int64_t) * 9) != hipSuccess ||
-                hipMalloc(&b->d_counters, sizeof(int) * 9) != hipSuccess)
-                return fail(CDBM_ENOMEM, "device allocation of the row-piece tables failed");
+        while (k < nq) close_range();
+        const int64_t nunits = (int64_t)table.size();
+        if (!b->d_range &&
+            (hipMalloc(&b->d_range, sizeof(int64_t) * 9) != hipSuccess ||
+             hipMalloc(&b->d_counters, sizeof(int) * 9) != hipSuccess))
+            return fail(CDBM_ENOMEM, "device allocation of the row-piece tables failed");
+        if (nunits > b->units_cap) {
+            if (b->d_units) (void)hipFree(b->d_units);
+            b->d_units = nullptr;
+            b->units_cap = 0;
+            if (hipMalloc(&b->d_units, sizeof(int) * 4 * nunits) != hipSuccess)
+                return fail(CDBM_ENOMEM, "device allocation of the unit table failed");
+            b->units_cap = nunits;
         }
-        if ((e = hipMemcpy(b->d_units, units.data(), sizeof(int64_t) * (n + 1),
+        std::vector<int> flat(4 * nunits);
+        for (int64_t u = 0; u < nunits; ++u) {
+            flat[4 * u] = table[u].g;
+            flat[4 * u + 1] = table[u].x0;
+            flat[4 * u + 2] = table[u].ya;
+            flat[4 * u + 3] = table[u].yb;
+        }
+        if ((e = hipMemcpy(b->d_units, flat.data(), sizeof(int) * 4 * nunits,
                            hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(b->d_geom, geom.data(), sizeof(int) * 3 * n, hipMemcpyHostToDevice)) !=
-                hipSuccess ||
             (e = hipMemcpy(b->d_range, range.data(), sizeof(int64_t) * (nq + 1),
                            hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemset(b->d_counters, 0, sizeof(int) * 9)) != hipSuccess ||
@@ -166,7 +208,8 @@ int apply_launch(cdbm_batch* b, const cdbm_batch_launch& l) {
 // The cache is a JSON object with one entry per line, keyed by
 // "<gfx arch>|<precision>|cells2^<k>|grids2^<m>" (k, m: floor of log2 of the
 // batch's cell and grid counts), each value the chosen launch and its time:
-//   "gfx950|mixed|cells2^25|grids2^6": {"layout": 1, "fill_rows": 14, "piece_rows": 192, "ms_per_step": 1.612},
+//   "gfx950|mixed|cells2^25|grids2^6": {"layout": 1, "fill_rows": 0, "piece_rows": 192, "tail_rows": 64, "ms_per_step": 1.512},
+// (an entry without tail_rows reads as tail_rows 0).
 
 struct TuneEntry {
     cdbm_batch_launch l;
@@ -211,9 +254,14 @@ std::vector<std::pair<std::string, TuneEntry>> read_cache(const char* path) {
         if (!brace) continue;
         TuneEntry e{};
         if (std::sscanf(brace, "{\"layout\": %d, \"fill_rows\": %d, \"piece_rows\": %d, "
-                               "\"ms_per_step\": %lf",
-                        &e.l.layout, &e.l.fill_rows, &e.l.piece_rows, &e.ms) != 4)
-            continue;
+                               "\"tail_rows\": %d, \"ms_per_step\": %lf",
+                        &e.l.layout, &e.l.fill_rows, &e.l.piece_rows, &e.l.tail_rows, &e.ms) != 5) {
+            e = TuneEntry{};
+            if (std::sscanf(brace, "{\"layout\": %d, \"fill_rows\": %d, \"piece_rows\": %d, "
+                                   "\"ms_per_step\": %lf",
+                            &e.l.layout, &e.l.fill_rows, &e.l.piece_rows, &e.ms) != 4)
+                continue;
+        }
         out.emplace_back(std::string(q0 + 1, q1), e);
     }
     std::fclose(fh);
@@ -229,9 +277,9 @@ void write_cache(const char* path, const std::vector<std::pair<std::string, Tune
         const TuneEntry& e = ents[k].second;
         std::fprintf(fh,
                      "\"%s\": {\"layout\": %d, \"fill_rows\": %d, \"piece_rows\": %d, "
-                     "\"ms_per_step\": %.6f}%s\n",
-                     ents[k].first.c_str(), e.l.layout, e.l.fill_rows, e.l.piece_rows, e.ms,
-                     k + 1 < ents.size() ? "," : "");
+                     "\"tail_rows\": %d, \"ms_per_step\": %.6f}%s\n",
+                     ents[k].first.c_str(), e.l.layout, e.l.fill_rows, e.l.piece_rows,
+                     e.l.tail_rows, e.ms, k + 1 < ents.size() ? "," : "");
     }
     std::fprintf(fh, "}\n");
     std::fclose(fh);
@@ -292,11 +340,18 @@ int autotune(cdbm_batch* b, const void* f_in, void* f_out, const char* cache_pat
             return rc;
         }
     // candidates: the contiguous split with three fill weights (the default
-    // first), and the row-piece form with three piece heights
+    // first), the row-piece form with three piece heights, and three
+    // row-piece forms with tails
+    // (on the 96-grid ensemble of 128^2 .. 1024^2 grids, mixed: 1.75-1.80 ms
+    // contiguous, 1.52-1.55 plain pieces of 128 or 192 rows, 1.44-1.46 with
+    // tails over the range of pieces below, within timing noise of each other)
     const cdbm_batch_launch cands[] = {
         {CDBM_BATCH_CONTIGUOUS, BATCH_FILL, 0, 0}, {CDBM_BATCH_CONTIGUOUS, 0, 0, 0},
         {CDBM_BATCH_CONTIGUOUS, 2 * BATCH_FILL, 0, 0}, {CDBM_BATCH_ROW_PIECES, 0, 128, 0},
-        {CDBM_BATCH_ROW_PIECES, 0, 192, 0}, {CDBM_BATCH_ROW_PIECES, 0, 256, 0},
+        {CDBM_BATCH_ROW_PIECES, 0, 192, 0},           {CDBM_BATCH_ROW_PIECES, 0, 160, 64},
+        {CDBM_BATCH_ROW_PIECES, 0, 192, 64},          {CDBM_BATCH_ROW_PIECES, 0, 320, 96},
+        {CDBM_BATCH_ROW_PIECES, 0, 320, 128},         {CDBM_BATCH_ROW_PIECES, 0, 384, 160},
+        {CDBM_BATCH_ROW_PIECES, 0, 448, 160},
     };
     TuneEntry best{cands[0], -1.0};
     for (const cdbm_batch_launch& c : cands) {

@@ -55,23 +55,26 @@ __global__ void __launch_bounds__(StripKernel<S>::NT) k_batch_step(const S* __re
     }
 }
 
-// Row-piece form.  Work units (grid g, row piece p, strip s) are numbered
-// grid by grid, piece by piece, strip by strip, so consecutive units are
-// neighbouring strips of the same rows.  The unit sequence is cut into nq
-// contiguous ranges of about equal weight (rows plus the pipeline fill), one
-// per XCD; block b (on XCD b % 8) takes the units of range b % nq in order,
-// one at a time, from that range's counter.  The blocks working at the same
-// time on one XCD then hold neighbouring strips at the same rows (their row
-// segments share DRAM pages, their halo lines that XCD's L2), and a block
-// that finishes early takes the next unit.  Every block leaves once its
-// range is used up; the last block to leave resets the counters for the
-// next launch.
+// Row-piece form.  The work is a table of units (grid, strip, first row,
+// end row), built on the host: each grid cut into row pieces, numbered grid
+// by grid, piece by piece, strip by strip, so that consecutive units are
+// neighbouring strips of the same rows, and optionally each grid's last
+// rows as smaller units after the pieces.  The table is cut into nq
+// contiguous ranges of about equal weight (rows plus the pipeline fill),
+// one per XCD; block b (on XCD b % 8) takes the units of range b % nq in
+// order, one at a time, from that range's counter.  The blocks working at
+// the same time on one XCD then hold neighbouring strips at the same rows
+// (their row segments share DRAM pages, their halo lines that XCD's L2),
+// and a block that finishes early takes the next unit.  Once its own range
+// is used up a block takes units from the other ranges in turn, so that no
+// XCD idles while another still has work; it leaves once every range is
+// used up (each counter only grows, so one pass over the ranges suffices),
+// and the last block to leave resets the counters for the next launch.
 template <typename S, bool VEC>
 __global__ void __launch_bounds__(StripKernel<S>::NT) k_batch_step_rows(
     const S* __restrict__ fin, S* __restrict__ fout, const KParams* __restrict__ Ks,
-    const int64_t* __restrict__ f_off, const int64_t* __restrict__ unit_start,
-    const int* __restrict__ geom, const int64_t* __restrict__ range_start, int nq,
-    int* __restrict__ counters) {
+    const int64_t* __restrict__ f_off, const int4* __restrict__ units,
+    const int64_t* __restrict__ range_start, int nq, int* __restrict__ counters) {
     using SK = StripKernel<S>;
     __shared__ __attribute__((aligned(16))) S F0[SK::F0_ELEMS];
     __shared__ __attribute__((aligned(16))) S F1[SK::F1_ELEMS];
@@ -80,27 +83,29 @@ __global__ void __launch_bounds__(StripKernel<S>::NT) k_batch_step_rows(
     // its last ring access and starts by writing F0 after the second barrier
     // below), and the two rings fill the whole 160 KiB of LDS
     volatile int64_t* s_u = reinterpret_cast<volatile int64_t*>(F0);
-    const int q = blockIdx.x % nq;
-    const int64_t u_end = range_start[q + 1];
-    int g = 0;
-    for (;;) {
-        if (threadIdx.x == 0) *s_u = range_start[q] + atomicAdd(&counters[q], 1);
-        __syncthreads();
-        // the same value in every lane: make it scalar, so that everything
-        // derived from it (grid, strip, rows) stays in scalar registers
-        const int64_t ul = *s_u;
-        const int64_t u =
-            (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(ul >> 32)) << 32) |
-                      (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)ul));
-        __syncthreads();   // every thread has read the unit before F0 is written again
-        if (u >= u_end) break;
-        while (unit_start[g + 1] <= u) ++g;   // a block's units only move forward
-        const int strips = geom[3 * g], rows = geom[3 * g + 2];
-        const int64_t v = u - unit_start[g];
-        const int p = (int)(v / strips), s = (int)(v - (int64_t)p * strips);
-        const KParams& K = Ks[g];
-        const int ya = p * rows, yb = min(K.ny, ya + rows);
-        SK::template run<VEC>(fin + f_off[g], fout + f_off[g], K, s * SK::TX, ya, yb, F0, F1);
+    const int q0 = blockIdx.x % nq;
+    for (int k = 0; k < nq; ++k) {
+        const int q = (q0 + k) % nq;
+        const int64_t u_begin = range_start[q], u_end = range_start[q + 1];
+        for (;;) {
+            if (threadIdx.x == 0) *s_u = u_begin + atomicAdd(&counters[q], 1);
+            __syncthreads();
+            // the same value in every lane: make it scalar, so that everything
+            // derived from it (grid, strip, rows) stays in scalar registers
+            const int64_t ul = *s_u;
+            const int64_t u = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(
+                                             (int)(ul >> 32))
+                                         << 32) |
+                                        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)ul));
+            __syncthreads();   // every thread has read the unit before F0 is written again
+            if (u >= u_end) break;
+            const int4 t = units[u];
+            const int g = __builtin_amdgcn_readfirstlane(t.x);
+            const int x0 = __builtin_amdgcn_readfirstlane(t.y);
+            const int ya = __builtin_amdgcn_readfirstlane(t.z);
+            const int yb = __builtin_amdgcn_readfirstlane(t.w);
+            SK::template run<VEC>(fin + f_off[g], fout + f_off[g], Ks[g], x0, ya, yb, F0, F1);
+        }
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -141,17 +146,16 @@ hipError_t launch_batch_step(const void* fin, void* fout, const KParams* Ks, con
 
 template <typename S>
 hipError_t launch_batch_step_rows(const void* fin, void* fout, const KParams* Ks,
-                                  const int64_t* f_off, const int64_t* unit_start, const int* geom,
+                                  const int64_t* f_off, const int* units,
                                   const int64_t* range_start, int nq, int* counters, int nblocks,
                                   bool chunked, hipStream_t st) {
+    const int4* t = reinterpret_cast<const int4*>(units);
     if (chunked && aligned16(fin, fout))
         hipLaunchKernelGGL((k_batch_step_rows<S, true>), dim3(nblocks), dim3(StripKernel<S>::NT), 0,
-                           st, (const S*)fin, (S*)fout, Ks, f_off, unit_start, geom, range_start, nq,
-                           counters);
+                           st, (const S*)fin, (S*)fout, Ks, f_off, t, range_start, nq, counters);
     else
         hipLaunchKernelGGL((k_batch_step_rows<S, false>), dim3(nblocks), dim3(StripKernel<S>::NT),
-                           0, st, (const S*)fin, (S*)fout, Ks, f_off, unit_start, geom, range_start,
-                           nq, counters);
+                           0, st, (const S*)fin, (S*)fout, Ks, f_off, t, range_start, nq, counters);
     return hipGetLastError();
 }
 
@@ -166,10 +170,10 @@ template hipError_t launch_batch_step<float>(const void*, void*, const KParams*,
 template hipError_t launch_batch_step<double>(const void*, void*, const KParams*, const int64_t*,
                                               const int64_t*, int, int, int, bool, hipStream_t);
 template hipError_t launch_batch_step_rows<float>(const void*, void*, const KParams*,
-                                                 const int64_t*, const int64_t*, const int*,
-                                                 const int64_t*, int, int*, int, bool, hipStream_t);
+                                                 const int64_t*, const int*, const int64_t*, int,
+                                                 int*, int, bool, hipStream_t);
 template hipError_t launch_batch_step_rows<double>(const void*, void*, const KParams*,
-                                                  const int64_t*, const int64_t*, const int*,
-                                                  const int64_t*, int, int*, int, bool, hipStream_t);
+                                                  const int64_t*, const int*, const int64_t*, int,
+                                                  int*, int, bool, hipStream_t);
 
 }  // namespace cdbm

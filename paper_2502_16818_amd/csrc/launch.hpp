@@ -97,14 +97,14 @@ hipError_t launch_batch_step(const void* fin, void* fout, const KParams* Ks, con
                              const int64_t* work_start, int ngrids, int fill, int nblocks,
                              bool chunked, hipStream_t st);
 
-// Row-piece form of the batched step: unit_start (ngrids + 1, device):
-// prefix sums of the grids' units (strips x row pieces); geom (3 ngrids,
-// device): strips, pieces and rows per piece of each grid; range_start
-// (nq + 1, device): the unit ranges of the nq counters; counters (nq + 1
-// ints, device, zero before the first launch; the kernel leaves them zero).
+// Row-piece form of the batched step: units (device, 16-byte aligned): four
+// ints per work unit, (grid, first column of its strip, first row, end
+// row), in queue order; range_start (nq + 1, device): the unit ranges of
+// the nq counters; counters (nq + 1 ints, device, zero before the first
+// launch; the kernel leaves them zero).
 template <typename S>
 hipError_t launch_batch_step_rows(const void* fin, void* fout, const KParams* Ks,
-                                  const int64_t* f_off, const int64_t* unit_start, const int* geom,
+                                  const int64_t* f_off, const int* units,
                                   const int64_t* range_start, int nq, int* counters, int nblocks,
                                   bool chunked, hipStream_t st);
 

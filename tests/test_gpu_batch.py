@@ -130,8 +130,10 @@ def test_batched_ensemble_workload_runs_and_conserves_mass():
         assert abs(m1 - m0[k]) <= 2e-6 * abs(m0[k])
 
 
-LAYOUTS = {"contiguous_fill0": (0, 0, 0), "contiguous_fill28": (0, 28, 0),
-           "rows16": (1, 0, 16), "rows96": (1, 0, 96), "rows384": (1, 0, 384)}
+LAYOUTS = {"contiguous_fill0": (0, 0, 0, 0), "contiguous_fill28": (0, 28, 0, 0),
+           "rows16": (1, 0, 16, 0), "rows96": (1, 0, 96, 0), "rows384": (1, 0, 384, 0),
+           "rows96_tail8": (1, 0, 96, 8), "rows192_tail64": (1, 0, 192, 64),
+           "rows384_tail96": (1, 0, 384, 96)}
 
 
 @pytest.mark.parametrize("layout", sorted(LAYOUTS))
@@ -146,9 +148,10 @@ def test_batch_layouts_are_bitwise_equal(precision, sizes, layout):
     b = Batch(_params(runs, precision))
     f = b.init([(r.rho, r.ux, r.uy, r.T) for r in runs])
     ref = b.step(f, nsteps=67)
-    lay, fill, rows = LAYOUTS[layout]
-    b.set_launch(lay, fill, rows)
-    assert b.get_launch() == {"layout": lay, "fill_rows": fill, "piece_rows": rows}
+    lay, fill, rows, tail = LAYOUTS[layout]
+    b.set_launch(lay, fill, rows, tail)
+    assert b.get_launch() == {"layout": lay, "fill_rows": fill, "piece_rows": rows,
+                              "tail_rows": tail}
     for rep in range(2):
         out = b.step(f, nsteps=67)
         torch.cuda.synchronize()
@@ -159,7 +162,8 @@ def test_batch_layouts_are_bitwise_equal(precision, sizes, layout):
 def test_batch_rejects_bad_layouts():
     from paper_2502_16818_amd import Batch, CdbmError
     b = Batch(_params(_mixed_set()[:2], FP64))
-    for bad in ((2, 14, 0), (0, -1, 0), (0, 2000, 0), (1, 0, 8), (1, 0, 100000)):
+    for bad in ((2, 14, 0), (0, -1, 0), (0, 2000, 0), (1, 0, 8), (1, 0, 100000), (1, 0, 96, 4),
+                (0, 14, 0, 16)):
         with pytest.raises(CdbmError) as e:
             b.set_launch(*bad)
         assert e.value.code == -1
@@ -202,7 +206,7 @@ def test_autotuned_ensemble_is_no_slower_than_the_default(tmp_path):
     assert len(entries) == 1
     (key, val), = entries.items()
     assert key.split("|")[1] == "mixed"
-    assert {k: val[k] for k in ("layout", "fill_rows", "piece_rows")} == chosen
+    assert {k: val[k] for k in ("layout", "fill_rows", "piece_rows", "tail_rows")} == chosen
     # a new batch of the same key takes the cached layout
     b2 = Batch(_params(runs, MIXED))
     assert b2.autotune(f, b2.empty_f(), cache) == chosen
