@@ -88,6 +88,27 @@ __device__ __forceinline__ void load_residual(const float* __restrict__ f, int64
     for (int k = 0; k < 4; ++k) r[k] = (double)f[(NV + k) * cells + c];
 }
 
+// An empty asm statement that takes the values as register operands: every
+// load feeding them completes before it, and none of them is used before
+// it, so the loads are issued together rather than one at a time.
+__device__ __forceinline__ void hold_values(float (&v)[4]) {
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]));
+}
+__device__ __forceinline__ void hold_values(float (&v)[NV + 4]) {
+    asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]),
+                 "+v"(v[6]), "+v"(v[7]), "+v"(v[8]), "+v"(v[9]));
+    asm volatile("" : "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]), "+v"(v[14]),
+                 "+v"(v[15]), "+v"(v[16]), "+v"(v[17]), "+v"(v[18]), "+v"(v[19]));
+}
+__device__ __forceinline__ void hold_values(float (&v)[4][6]) {
+    asm volatile("" : "+v"(v[0][0]), "+v"(v[0][1]), "+v"(v[0][2]), "+v"(v[0][3]), "+v"(v[0][4]),
+                 "+v"(v[0][5]), "+v"(v[1][0]), "+v"(v[1][1]), "+v"(v[1][2]), "+v"(v[1][3]),
+                 "+v"(v[1][4]), "+v"(v[1][5]));
+    asm volatile("" : "+v"(v[2][0]), "+v"(v[2][1]), "+v"(v[2][2]), "+v"(v[2][3]), "+v"(v[2][4]),
+                 "+v"(v[2][5]), "+v"(v[3][0]), "+v"(v[3][1]), "+v"(v[3][2]), "+v"(v[3][3]),
+                 "+v"(v[3][4]), "+v"(v[3][5]));
+}
+
 // Compensated initial state: f = f^eq rounded to float, r = the conserved
 // moments of what the rounding removed.
 __global__ void __launch_bounds__(256) k_init_comp(const double* __restrict__ rho,
@@ -322,41 +343,79 @@ __global__ void __launch_bounds__(256) k_stage_comp(const float* __restrict__ fi
         ld.ys[o + 2] = wrap_or_clamp(y + o, K.ny, K.bcy);
     }
     const int64_t c = (int64_t)y * K.nx + x;
-    float f[NV];
-    double fd[NV];
+    // The loads of a cell's 16 values and residual, and then of each group's
+    // stencils, are issued together and held by one empty asm statement
+    // before any is used: left to itself the compiler fetched one value at a
+    // time (load, wait, convert) to save registers, and the stage took twice
+    // as long.
+    float f[NV + 4];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        f[i] = ld(i, 0, 0);
-        fd[i] = (double)f[i];
-    }
-    double r[4];
-    load_residual(fin, cells, c, r);
+    for (int i = 0; i < NV; ++i) f[i] = ld(i, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) f[NV + k] = fin[(NV + k) * cells + c];
+    hold_values(f);
+    double fd[NV], r[4];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) fd[i] = (double)f[i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = (double)f[NV + k];
     Parity g;
     to_parity(fd, g);
     const Macro m = macro_compensated(g, r, K);
     double neq[NV];
     nonequilibrium(g, m, K, K.a, neq);
     const double nza = K.nzq[STAGE2][0], nzd = K.nzq[STAGE2][1];
-    auto ldd = [&](int i, int ox, int oy) { return (double)ld(i, ox, oy); };
     double lost[NV];
+    // groups of four velocities (axis group: one stencil direction each,
+    // diagonal group: two); st[k][0..2] the x stencil of velocity i0 + k
+    // without its centre, st[k][3..5] the y stencil, upwind first
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        const double cx = STAGE2 ? K.cxh[i] : K.cx[i];
-        const double cy = STAGE2 ? K.cyh[i] : K.cy[i];
-        double adv = 0.0;
-        if (SX[i] > 0) adv = cx * nnd_pos<double>(ldd(i, -2, 0), ldd(i, -1, 0), fd[i], ldd(i, 1, 0));
-        else if (SX[i] < 0)
-            adv = cx * nnd_neg<double>(ldd(i, -1, 0), fd[i], ldd(i, 1, 0), ldd(i, 2, 0));
-        if (SY[i] > 0) adv += cy * nnd_pos<double>(ldd(i, 0, -2), ldd(i, 0, -1), fd[i], ldd(i, 0, 1));
-        else if (SY[i] < 0)
-            adv += cy * nnd_neg<double>(ldd(i, 0, -1), fd[i], ldd(i, 0, 1), ldd(i, 0, 2));
-        const double coll = ((i & 4) ? nzd : nza) * neq[i];
-        double yv = adv;
-        if (STAGE2) yv += 0.5 * fd[i] + 0.5 * (double)base[i * cells + c];
-        else yv += fd[i];
-        const float o = (float)(yv + coll);
-        fout[i * cells + c] = o;
-        lost[i] = yv - (double)o;
+    for (int i0 = 0; i0 < NV; i0 += 4) {
+        float st[4][6];
+        float hb[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = i0 + k;
+            if (SX[i] > 0) {
+                st[k][0] = ld(i, -2, 0); st[k][1] = ld(i, -1, 0); st[k][2] = ld(i, 1, 0);
+            } else if (SX[i] < 0) {
+                st[k][0] = ld(i, -1, 0); st[k][1] = ld(i, 1, 0); st[k][2] = ld(i, 2, 0);
+            } else {
+                st[k][0] = st[k][1] = st[k][2] = 0.0f;
+            }
+            if (SY[i] > 0) {
+                st[k][3] = ld(i, 0, -2); st[k][4] = ld(i, 0, -1); st[k][5] = ld(i, 0, 1);
+            } else if (SY[i] < 0) {
+                st[k][3] = ld(i, 0, -1); st[k][4] = ld(i, 0, 1); st[k][5] = ld(i, 0, 2);
+            } else {
+                st[k][3] = st[k][4] = st[k][5] = 0.0f;
+            }
+            hb[k] = STAGE2 ? base[i * cells + c] : 0.0f;
+        }
+        hold_values(st);
+        if (STAGE2) hold_values(hb);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = i0 + k;
+            const double cx = STAGE2 ? K.cxh[i] : K.cx[i];
+            const double cy = STAGE2 ? K.cyh[i] : K.cy[i];
+            double adv = 0.0;
+            if (SX[i] > 0)
+                adv = cx * nnd_pos<double>(st[k][0], st[k][1], fd[i], st[k][2]);
+            else if (SX[i] < 0)
+                adv = cx * nnd_neg<double>(st[k][0], fd[i], st[k][1], st[k][2]);
+            if (SY[i] > 0)
+                adv += cy * nnd_pos<double>(st[k][3], st[k][4], fd[i], st[k][5]);
+            else if (SY[i] < 0)
+                adv += cy * nnd_neg<double>(st[k][3], fd[i], st[k][4], st[k][5]);
+            const double coll = ((i & 4) ? nzd : nza) * neq[i];
+            double yv = adv;
+            if (STAGE2) yv += 0.5 * fd[i] + 0.5 * (double)hb[k];
+            else yv += fd[i];
+            const float o = (float)(yv + coll);
+            fout[i * cells + c] = o;
+            lost[i] = yv - (double)o;
+        }
     }
     Parity gl;
     to_parity(lost, gl);
