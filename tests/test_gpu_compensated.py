@@ -107,12 +107,23 @@ def test_steps_against_fp64_oracle(run):
         if prec == COMP:
             fmax = float(ref.abs().max())
             ferr = float(np.abs(to_np(out[:16]) - ref.numpy()).max()) / fmax
+            tne = to_np(s.tne(out))
         s.close()
-    print(f"  mixed {errs[MIXED]}\n  compensated {errs[COMP]}; f {ferr:.2e} of max|f|")
+    # nonequilibrium measures: the mixed form's bound (1 % of their largest
+    # value plus 1e-5 of the FP32 rounding scale max sum_i |f_i Psi_i|)
+    d_ref = C.nonequilibrium(ref, p).numpy()
+    vel, eta = C.discrete_velocities(p.v, p.eta)
+    _, ux, uy, _ = C.fields(ref, p)
+    M = C.moment_matrix(ux.reshape(-1), uy.reshape(-1), vel, eta)[:, 4:, :]
+    scale = float(torch.einsum("nri,ni->nr", M.abs(), ref.reshape(16, -1).t().abs()).max())
+    d_err = float(np.abs(tne - d_ref).max())
+    print(f"  mixed {errs[MIXED]}\n  compensated {errs[COMP]}; f {ferr:.2e} of max|f|; "
+          f"TNE {d_err / (np.abs(d_ref).max() + 1e-3 * scale):.2e}")
     e = errs[COMP]
     assert e["rho"] < 4e-7 and e["T"] < 4e-7
     assert e["ux"] < 2.5e-6 and e["uy"] < 2.5e-6
     assert ferr < 3e-6
+    assert d_err <= 1e-2 * np.abs(d_ref).max() + 1e-5 * scale
 
 
 def test_split_and_auto_forms_are_bitwise_equal():

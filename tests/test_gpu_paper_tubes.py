@@ -1,6 +1,7 @@
 """The paper's tube runs at the paper's shapes on the HIP path (Secs. 3.1-3.3):
 parity with the FP64 oracle over the first steps, then the full run against
-the exact solution of the Riemann problem."""
+the exact solution of the Riemann problem in each precision form (FP64, mixed
+and compensated mixed)."""
 import numpy as np
 import pytest
 
@@ -10,7 +11,7 @@ from helpers import oracle_after, rel_max, to_np
 
 pytestmark = pytest.mark.gpu
 
-FP64 = 0
+FP64, MIXED, COMP = 0, 1, 2   # CDBM_FP64, CDBM_MIXED, CDBM_MIXED_COMP
 
 
 def _case(name):
@@ -27,10 +28,10 @@ def _case(name):
     raise KeyError(name)
 
 
-def _gpu_run(run, nsteps):
+def _gpu_run(run, nsteps, precision=FP64):
     from paper_2502_16818_amd import Solver
-    print(f"[case] {run.name} {run.nx}x{run.ny} steps={nsteps}", flush=True)
-    s = Solver.from_run(run, FP64)
+    print(f"[case] {run.name} {run.nx}x{run.ny} steps={nsteps} precision={precision}", flush=True)
+    s = Solver.from_run(run, precision)
     f = s.init(run.rho, run.ux, run.uy, run.T)
     out = s.step(f, nsteps=nsteps)
     fields = [to_np(a)[0] for a in s.moments(out)]
@@ -56,10 +57,11 @@ def test_paper_tube_first_steps_match_oracle(name):
 GATES = {"sod": (0.02, 3.0), "lax": (0.02, 3.0), "shock": (0.02, 3.0)}
 
 
+@pytest.mark.parametrize("precision", [FP64, MIXED, COMP])
 @pytest.mark.parametrize("name", ["sod", "lax", "shock"])
-def test_paper_tube_against_exact_riemann(name):
+def test_paper_tube_against_exact_riemann(name, precision):
     run, L, R, gamma, x0 = _case(name)
-    _, (rho, ux, _, T) = _gpu_run(run, run.steps)
+    _, (rho, ux, _, T) = _gpu_run(run, run.steps, precision)
     x = W.cell_centres(run.nx, run.dx)
     t = run.steps * run.dt
     re, ue, pe = Rm.sample(L, R, gamma, (x - x0) / t)
