@@ -81,9 +81,9 @@ enum { CDBM_STEP_AUTO = 0, CDBM_STEP_FUSED = 1, CDBM_STEP_SPLIT = 2, CDBM_STEP_F
  *               CDBM_MIXED_COMP: f stored in float as in CDBM_MIXED, each
  *               stage's arithmetic in double as in CDBM_FP64, and a
  *               compensation of the conserved moments: each cell also
- *               stores, in float, the
- *               part r of its mass, momentum and energy that rounding f to
- *               float removed: the cell's conserved moments are
+ *               stores, in float, the part r of its mass, momentum and
+ *               energy that rounding f to float removed; the cell's
+ *               conserved moments are
  *               sum_i f_i psi_i + r (psi = 1, v_x, v_y, |v|^2 + eta^2), in
  *               the equilibrium, in cdbm_moments and in the totals.  A stage
  *               forms each new f_i in double, rounds it to float, and adds
