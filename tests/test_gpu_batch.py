@@ -213,3 +213,13 @@ def test_autotuned_ensemble_is_no_slower_than_the_default(tmp_path):
     assert b2.get_launch() == chosen
     b.close()
     b2.close()
+    # an entry written without tail_rows (the earlier cache format) reads as
+    # tail_rows 0
+    with open(cache, "w") as fh:
+        fh.write("{\n" + json.dumps(key) + ': {"layout": 1, "fill_rows": 0, "piece_rows": 192, '
+                 '"ms_per_step": 1.6}\n}\n')
+    b3 = Batch(_params(runs, MIXED))
+    want = {"layout": 1, "fill_rows": 0, "piece_rows": 192, "tail_rows": 0}
+    assert b3.autotune(f, b3.empty_f(), cache) == want
+    assert b3.get_launch() == want
+    b3.close()
